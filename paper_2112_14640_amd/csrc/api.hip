@@ -1,0 +1,372 @@
+// C ABI of libdirac: argument validation, dispatch to the kernel launchers and error strings.
+// Validation runs before any launch; no entry point throws or aborts.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace dirac {
+
+namespace {
+thread_local std::string g_last_error;
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+    const char* pa = static_cast<const char*>(a);
+    const char* pb = static_cast<const char*>(b);
+    return pa < pb + nb && pb < pa + na;
+}
+
+bool aligned(const void* p, size_t a) { return reinterpret_cast<uintptr_t>(p) % a == 0; }
+
+// Tuned RHS-per-thread overrides, [op][prec]; 0 = automatic.
+int g_rb_override[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+
+int check_common(dirac_op op, dirac_prec prec, int nc, int nv, const dirac_dims* dims, Geom& g) {
+    if (op < DIRAC_WILSON || op > DIRAC_STAGGERED) return fail(DIRAC_EINVAL, "unknown operator");
+    if (prec < DIRAC_FP64 || prec > DIRAC_BF16) return fail(DIRAC_EINVAL, "unknown precision");
+    if (!dims) return fail(DIRAC_EINVAL, "dims is NULL");
+    for (int mu = 0; mu < 4; ++mu) {
+        if (dims->n[mu] < 2) return fail(DIRAC_EINVAL, "lattice extents must be >= 2");
+        if (op == DIRAC_STAGGERED && (dims->n[mu] & 1)) return fail(DIRAC_EINVAL, "staggered extents must be even");
+    }
+    if (nv < 1 || nv > 256) return fail(DIRAC_EINVAL, "nv must be in 1..256");
+    if (nc < 1 || nc > 4) return fail(DIRAC_EUNSUPPORTED, "nc must be in 1..4");
+    g.nx = dims->n[0];
+    g.ny = dims->n[1];
+    g.nz = dims->n[2];
+    g.nt = dims->n[3];
+    g.vol = static_cast<int64_t>(g.nx) * g.ny * g.nz * g.nt;
+    g.apbc = dims->antiperiodic_t ? 1 : 0;
+    return DIRAC_OK;
+}
+
+int64_t rows_of(dirac_op op, int nc, const Geom& g) { return g.vol * nc * (op == DIRAC_STAGGERED ? 1 : 4); }
+
+size_t gauge_bytes(dirac_op op, dirac_prec prec, int nc, const Geom& g) {
+    const int dirs = op == DIRAC_BRILLOUIN ? 40 : 4;
+    return static_cast<size_t>(g.vol) * dirs * nc * nc * gauge_complex_bytes(prec);
+}
+
+int stencil(dirac_op op, dirac_prec prec, const void* gauge, const void* u, void* v, double mass, int nc, int nv,
+            const dirac_dims* dims, void* stream, bool dag) {
+    Geom g;
+    int rc = check_common(op, prec, nc, nv, dims, g);
+    if (rc) return rc;
+    if (!gauge || !u || !v) return fail(DIRAC_EINVAL, "NULL gauge or vector pointer");
+    const size_t vb = static_cast<size_t>(rows_of(op, nc, g)) * nv * complex_bytes(prec);
+    if (overlap(u, vb, v, vb)) return fail(DIRAC_EINVAL, "input and output vectors overlap");
+    if (overlap(gauge, gauge_bytes(op, prec, nc, g), v, vb)) return fail(DIRAC_EINVAL, "gauge and output overlap");
+    if (!aligned(u, complex_bytes(prec)) || !aligned(v, complex_bytes(prec)) ||
+        !aligned(gauge, gauge_complex_bytes(prec)))
+        return fail(DIRAC_EINVAL, "misaligned pointer");
+    if (!std::isfinite(mass)) return fail(DIRAC_EINVAL, "mass is not finite");
+    StencilArgs a{prec, nc, nv, choose_rb(op, prec, nc, nv), dag, mass, g, gauge, u, v};
+    hipStream_t st = as_stream(stream);
+    switch (op) {
+        case DIRAC_WILSON: rc = launch_wilson(a, st); break;
+        case DIRAC_BRILLOUIN: rc = launch_brillouin(a, st); break;
+        case DIRAC_STAGGERED: rc = launch_staggered(a, st); break;
+    }
+    if (rc) return fail(rc, "stencil launch rejected");
+    DIRAC_HIP(hipGetLastError());
+    return DIRAC_OK;
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int status, const std::string& msg) {
+    g_last_error = msg;
+    return status;
+}
+
+int check_hip(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return DIRAC_EHIP;
+}
+
+int choose_rb(dirac_op op, dirac_prec prec, int nc, int nv) {
+    const int o = g_rb_override[op][prec];
+    if (o > 0 && nv % o == 0) return o;
+    (void)nc;
+    switch (op) {
+        case DIRAC_WILSON:
+            if (prec == DIRAC_FP64) return 1;
+            return nv % 2 == 0 ? 2 : 1;
+        case DIRAC_STAGGERED:
+            if (prec != DIRAC_FP64 && nv % 4 == 0) return 4;
+            return nv % 2 == 0 ? 2 : 1;
+        case DIRAC_BRILLOUIN:
+            return 1;
+    }
+    return 1;
+}
+
+size_t solver_workspace_bytes(dirac_op op, int solver, dirac_prec outer, dirac_prec inner, int nc, int nv,
+                              const Geom& g, int scheme);
+int run_solver(int solver, dirac_op op, dirac_prec outer, dirac_prec inner, const void* gauge_hi,
+               const void* gauge_lo, const void* b, void* x, double mass, int nc, int nv, const Geom& g, double tol,
+               int maxit, void* workspace, size_t ws_bytes, dirac_solve_info* info, const dirac_solve_opts* opts,
+               hipStream_t st);
+
+}  // namespace dirac
+
+using namespace dirac;
+
+extern "C" {
+
+int dirac_apply(dirac_op op, dirac_prec prec, const void* gauge, const void* u, void* v, double mass, int nc, int nv,
+                const dirac_dims* dims, void* stream) {
+    return stencil(op, prec, gauge, u, v, mass, nc, nv, dims, stream, false);
+}
+
+int dirac_apply_dagger(dirac_op op, dirac_prec prec, const void* gauge, const void* u, void* v, double mass, int nc,
+                       int nv, const dirac_dims* dims, void* stream) {
+    return stencil(op, prec, gauge, u, v, mass, nc, nv, dims, stream, true);
+}
+
+int dirac_apply_normal(dirac_op op, dirac_prec prec, const void* gauge, const void* u, void* v, void* tmp,
+                       double mass, int nc, int nv, const dirac_dims* dims, void* stream) {
+    Geom g;
+    int rc = check_common(op, prec, nc, nv, dims, g);
+    if (rc) return rc;
+    if (!tmp) return fail(DIRAC_EINVAL, "NULL scratch vector");
+    const size_t vb = static_cast<size_t>(rows_of(op, nc, g)) * nv * complex_bytes(prec);
+    if (u && (overlap(u, vb, tmp, vb) || (v && overlap(v, vb, tmp, vb))))
+        return fail(DIRAC_EINVAL, "scratch vector overlaps input or output");
+    rc = stencil(op, prec, gauge, u, tmp, mass, nc, nv, dims, stream, false);
+    if (rc) return rc;
+    return stencil(op, prec, gauge, tmp, v, mass, nc, nv, dims, stream, true);
+}
+
+int dirac_brillouin_links(dirac_prec prec, const void* U, void* W, int nc, const dirac_dims* dims, void* stream) {
+    Geom g;
+    int rc = check_common(DIRAC_BRILLOUIN, prec, nc, 1, dims, g);
+    if (rc) return rc;
+    if (!U || !W) return fail(DIRAC_EINVAL, "NULL link pointer");
+    if (overlap(U, gauge_bytes(DIRAC_WILSON, prec, nc, g), W, gauge_bytes(DIRAC_BRILLOUIN, prec, nc, g)))
+        return fail(DIRAC_EINVAL, "U and W overlap");
+    if (!aligned(U, gauge_complex_bytes(prec)) || !aligned(W, gauge_complex_bytes(prec)))
+        return fail(DIRAC_EINVAL, "misaligned pointer");
+    rc = launch_brillouin_links(prec, nc, g, U, W, as_stream(stream));
+    if (rc) return fail(rc, "link launch rejected");
+    DIRAC_HIP(hipGetLastError());
+    return DIRAC_OK;
+}
+
+int dirac_force(dirac_op op, const void* U, const void* psi, const void* chi, void* gout, double coeff, int nc, int nv,
+                const dirac_dims* dims, void* stream) {
+    Geom g;
+    int rc = check_common(op, DIRAC_FP64, nc, nv, dims, g);
+    if (rc) return rc;
+    if (op == DIRAC_BRILLOUIN) return fail(DIRAC_EUNSUPPORTED, "force is implemented for Wilson and staggered");
+    if (!psi || !chi || !gout) return fail(DIRAC_EINVAL, "NULL pointer");
+    const size_t vb = static_cast<size_t>(rows_of(op, nc, g)) * nv * 16;
+    const size_t gb = gauge_bytes(op, DIRAC_FP64, nc, g);
+    if (overlap(psi, vb, gout, gb) || overlap(chi, vb, gout, gb)) return fail(DIRAC_EINVAL, "output overlaps inputs");
+    rc = launch_force(op, nc, nv, g, U, psi, chi, gout, coeff, as_stream(stream));
+    if (rc) return fail(rc, "force launch rejected");
+    DIRAC_HIP(hipGetLastError());
+    return DIRAC_OK;
+}
+
+int dirac_project_su(const void* U, const void* g, void* F, int nc, int64_t nlinks, void* stream) {
+    if (!U || !g || !F) return fail(DIRAC_EINVAL, "NULL pointer");
+    if (nc < 1 || nc > 4) return fail(DIRAC_EUNSUPPORTED, "nc must be in 1..4");
+    if (nlinks < 0) return fail(DIRAC_EINVAL, "negative link count");
+    if (nlinks == 0) return DIRAC_OK;
+    const size_t b = static_cast<size_t>(nlinks) * nc * nc * 16;
+    if (overlap(U, b, F, b)) return fail(DIRAC_EINVAL, "F overlaps U");
+    int rc = launch_project_su(nc, nlinks, U, g, F, as_stream(stream));
+    if (rc) return fail(rc, "projection launch rejected");
+    DIRAC_HIP(hipGetLastError());
+    return DIRAC_OK;
+}
+
+static int blas_check(dirac_prec p, int64_t nrows, int nv) {
+    if (p < DIRAC_FP64 || p > DIRAC_BF16) return fail(DIRAC_EINVAL, "unknown precision");
+    if (nv < 1 || nv > 256) return fail(DIRAC_EINVAL, "nv must be in 1..256");
+    if (nrows < 0) return fail(DIRAC_EINVAL, "negative row count");
+    return DIRAC_OK;
+}
+
+size_t dirac_blas_workspace_bytes(int nv) {
+    return (nv < 1 || nv > 256) ? 0 : reduce_partial_doubles(nv) * sizeof(double);
+}
+
+int dirac_norm2(dirac_prec prec, const void* x, int64_t nrows, int nv, double* out, void* workspace, size_t ws_bytes,
+                void* stream) {
+    int rc = blas_check(prec, nrows, nv);
+    if (rc) return rc;
+    if (!x || !out || !workspace) return fail(DIRAC_EINVAL, "NULL pointer");
+    if (ws_bytes < dirac_blas_workspace_bytes(nv)) return fail(DIRAC_EWORKSPACE, "BLAS workspace too small");
+    rc = blas_norm2(prec, x, nrows, nv, static_cast<double*>(workspace), out, as_stream(stream));
+    if (rc) return fail(rc, "norm launch rejected");
+    DIRAC_HIP(hipGetLastError());
+    return DIRAC_OK;
+}
+
+int dirac_dot(dirac_prec prec_x, const void* x, dirac_prec prec_y, const void* y, int64_t nrows, int nv, double* out,
+              void* workspace, size_t ws_bytes, void* stream) {
+    int rc = blas_check(prec_x, nrows, nv);
+    if (!rc) rc = blas_check(prec_y, nrows, nv);
+    if (rc) return rc;
+    if (!x || !y || !out || !workspace) return fail(DIRAC_EINVAL, "NULL pointer");
+    if (ws_bytes < dirac_blas_workspace_bytes(nv)) return fail(DIRAC_EWORKSPACE, "BLAS workspace too small");
+    rc = blas_dot(prec_x, x, prec_y, y, nrows, nv, static_cast<double*>(workspace), out, as_stream(stream));
+    if (rc) return fail(rc, "dot launch rejected");
+    DIRAC_HIP(hipGetLastError());
+    return DIRAC_OK;
+}
+
+int dirac_caxpy(dirac_prec prec_x, const void* x, dirac_prec prec_y, void* y, const double* a, int64_t nrows, int nv,
+                void* stream) {
+    int rc = blas_check(prec_x, nrows, nv);
+    if (!rc) rc = blas_check(prec_y, nrows, nv);
+    if (rc) return rc;
+    if (!x || !y || !a) return fail(DIRAC_EINVAL, "NULL pointer");
+    if (overlap(x, nrows * nv * complex_bytes(prec_x), y, nrows * nv * complex_bytes(prec_y)))
+        return fail(DIRAC_EINVAL, "x and y overlap");
+    rc = blas_caxpy(prec_x, x, prec_y, y, a, nrows, nv, as_stream(stream));
+    if (rc) return fail(rc, "caxpy launch rejected");
+    DIRAC_HIP(hipGetLastError());
+    return DIRAC_OK;
+}
+
+int dirac_cxpay(dirac_prec prec_x, const void* x, dirac_prec prec_y, void* y, const double* a, int64_t nrows, int nv,
+                void* stream) {
+    int rc = blas_check(prec_x, nrows, nv);
+    if (!rc) rc = blas_check(prec_y, nrows, nv);
+    if (rc) return rc;
+    if (!x || !y || !a) return fail(DIRAC_EINVAL, "NULL pointer");
+    if (overlap(x, nrows * nv * complex_bytes(prec_x), y, nrows * nv * complex_bytes(prec_y)))
+        return fail(DIRAC_EINVAL, "x and y overlap");
+    rc = blas_cxpay(prec_x, x, prec_y, y, a, nrows, nv, as_stream(stream));
+    if (rc) return fail(rc, "cxpay launch rejected");
+    DIRAC_HIP(hipGetLastError());
+    return DIRAC_OK;
+}
+
+int dirac_cast(dirac_prec prec_x, const void* x, dirac_prec prec_y, void* y, int64_t ncomplex, void* stream) {
+    int rc = blas_check(prec_x, ncomplex, 1);
+    if (!rc) rc = blas_check(prec_y, ncomplex, 1);
+    if (rc) return rc;
+    if (!x || !y) return fail(DIRAC_EINVAL, "NULL pointer");
+    if (ncomplex == 0) return DIRAC_OK;
+    if (overlap(x, ncomplex * complex_bytes(prec_x), y, ncomplex * complex_bytes(prec_y)))
+        return fail(DIRAC_EINVAL, "x and y overlap");
+    rc = blas_cast(prec_x, x, prec_y, y, ncomplex, as_stream(stream));
+    if (rc) return fail(rc, "cast launch rejected");
+    DIRAC_HIP(hipGetLastError());
+    return DIRAC_OK;
+}
+
+int dirac_gamma5(dirac_op op, dirac_prec prec, const void* x, void* y, int nc, int nv, const dirac_dims* dims,
+                 void* stream) {
+    Geom g;
+    int rc = check_common(op, prec, nc, nv, dims, g);
+    if (rc) return rc;
+    if (!x || !y) return fail(DIRAC_EINVAL, "NULL pointer");
+    rc = blas_gamma5(op, prec, x, y, nc, nv, g, as_stream(stream));
+    if (rc) return fail(rc, "gamma5 launch rejected");
+    DIRAC_HIP(hipGetLastError());
+    return DIRAC_OK;
+}
+
+size_t dirac_solver_workspace_bytes(dirac_op op, int solver, dirac_prec outer, dirac_prec inner, int nc, int nv,
+                                    const dirac_dims* dims) {
+    Geom g;
+    if (check_common(op, outer, nc, nv, dims, g)) return 0;
+    if (inner < DIRAC_FP64 || inner > DIRAC_BF16 || solver < 0 || solver > 1) return 0;
+    // room for either mixed scheme
+    const size_t a = solver_workspace_bytes(op, solver, outer, inner, nc, nv, g, 0);
+    const size_t b = solver_workspace_bytes(op, solver, outer, inner, nc, nv, g, 1);
+    return a > b ? a : b;
+}
+
+static int solve(int solver, dirac_op op, dirac_prec outer, dirac_prec inner, const void* gauge_hi,
+                 const void* gauge_lo, const void* b, void* x, double mass, int nc, int nv, const dirac_dims* dims,
+                 double tol, int maxit, void* workspace, size_t ws_bytes, dirac_solve_info* info,
+                 const dirac_solve_opts* opts, void* stream) {
+    Geom g;
+    int rc = check_common(op, outer, nc, nv, dims, g);
+    if (rc) return rc;
+    if (outer == DIRAC_BF16) return fail(DIRAC_EUNSUPPORTED, "outer precision must be FP64 or FP32");
+    if (inner < DIRAC_FP64 || inner > DIRAC_BF16) return fail(DIRAC_EINVAL, "unknown inner precision");
+    const bool mixed = inner != outer;
+    if (mixed && (outer != DIRAC_FP64 || inner == DIRAC_FP64))
+        return fail(DIRAC_EUNSUPPORTED, "mixed precision needs an FP64 outer and an FP32/BF16 inner precision");
+    if (solver == 1 && op == DIRAC_STAGGERED) return fail(DIRAC_EUNSUPPORTED, "BiCGstab is for Wilson and Brillouin");
+    if (!gauge_hi || !b || !x || !workspace || (mixed && !gauge_lo)) return fail(DIRAC_EINVAL, "NULL pointer");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(DIRAC_EINVAL, "tolerance must be positive");
+    if (maxit < 0) return fail(DIRAC_EINVAL, "maxit must be >= 0");
+    if (!std::isfinite(mass)) return fail(DIRAC_EINVAL, "mass is not finite");
+    const size_t vb = static_cast<size_t>(rows_of(op, nc, g)) * nv * complex_bytes(outer);
+    if (overlap(b, vb, x, vb)) return fail(DIRAC_EINVAL, "b and x overlap");
+    if (overlap(workspace, ws_bytes, x, vb) || overlap(workspace, ws_bytes, b, vb))
+        return fail(DIRAC_EINVAL, "workspace overlaps b or x");
+    if (info) {
+        info->iters = info->outer_iters = info->reason = 0;
+        info->hist_len = 0;
+    }
+    return run_solver(solver, op, outer, inner, gauge_hi, gauge_lo, b, x, mass, nc, nv, g, tol, maxit, workspace,
+                      ws_bytes, info, opts, as_stream(stream));
+}
+
+int cg_solve(dirac_op op, dirac_prec outer, dirac_prec inner, const void* gauge_hi, const void* gauge_lo,
+             const void* b, void* x, double mass, int nc, int nv, const dirac_dims* dims, double tol, int maxit,
+             void* workspace, size_t ws_bytes, dirac_solve_info* info, const dirac_solve_opts* opts, void* stream) {
+    return solve(0, op, outer, inner, gauge_hi, gauge_lo, b, x, mass, nc, nv, dims, tol, maxit, workspace, ws_bytes,
+                 info, opts, stream);
+}
+
+int bicgstab_solve(dirac_op op, dirac_prec outer, dirac_prec inner, const void* gauge_hi, const void* gauge_lo,
+                   const void* b, void* x, double mass, int nc, int nv, const dirac_dims* dims, double tol, int maxit,
+                   void* workspace, size_t ws_bytes, dirac_solve_info* info, const dirac_solve_opts* opts,
+                   void* stream) {
+    return solve(1, op, outer, inner, gauge_hi, gauge_lo, b, x, mass, nc, nv, dims, tol, maxit, workspace, ws_bytes,
+                 info, opts, stream);
+}
+
+int dirac_set_rhs_per_thread(dirac_op op, dirac_prec prec, int rb) {
+    if (op < DIRAC_WILSON || op > DIRAC_STAGGERED || prec < DIRAC_FP64 || prec > DIRAC_BF16)
+        return fail(DIRAC_EINVAL, "unknown operator or precision");
+    const int maxrb = op == DIRAC_BRILLOUIN ? 2 : 4;
+    if (rb != 0 && rb != 1 && rb != 2 && rb != 4) return fail(DIRAC_EINVAL, "rb must be 0, 1, 2 or 4");
+    if (rb > maxrb) return fail(DIRAC_EUNSUPPORTED, "rb not instantiated for this operator");
+    g_rb_override[op][prec] = rb;
+    return DIRAC_OK;
+}
+
+double dirac_flops_per_site(dirac_op op, int nc) {
+    const double n = nc;
+    switch (op) {
+        case DIRAC_WILSON: return 128.0 * n * n + 72.0 * n;
+        case DIRAC_BRILLOUIN: return 2560.0 * n * n + 2376.0 * n;
+        case DIRAC_STAGGERED: return 64.0 * n * n + 2.0 * n;
+    }
+    return 0.0;
+}
+
+const char* dirac_error_string(int status) {
+    switch (status) {
+        case DIRAC_OK: return "ok";
+        case DIRAC_NOT_CONVERGED: return "solver did not converge (iteration limit or stagnation)";
+        case DIRAC_EINVAL: return "invalid argument";
+        case DIRAC_EUNSUPPORTED: return "unsupported configuration";
+        case DIRAC_EHIP: return "HIP runtime error";
+        case DIRAC_EWORKSPACE: return "workspace too small";
+        case DIRAC_ENONFINITE: return "non-finite value in a norm";
+    }
+    return "unknown status";
+}
+
+const char* dirac_last_error(void) { return g_last_error.c_str(); }
+
+const char* dirac_version(void) { return "libdirac 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+// Internal launcher interface between the C ABI / solvers and the kernel files.
+#pragma once
+
+#include "common.h"
+
+namespace dirac {
+
+struct StencilArgs {
+    dirac_prec prec;
+    int nc;
+    int nv;
+    int rb;  // right-hand sides per thread (divides nv)
+    bool dagger;
+    double mass;
+    Geom g;
+    const void* gauge;
+    const void* in;
+    void* out;
+};
+
+// Stencil launches (asynchronous; arguments already validated).
+int launch_wilson(const StencilArgs& a, hipStream_t st);
+int launch_staggered(const StencilArgs& a, hipStream_t st);
+int launch_brillouin(const StencilArgs& a, hipStream_t st);
+int launch_brillouin_links(dirac_prec prec, int nc, const Geom& g, const void* U, void* W, hipStream_t st);
+int launch_force(dirac_op op, int nc, int nv, const Geom& g, const void* U, const void* psi, const void* chi,
+                 void* gout, double coeff, hipStream_t st);
+int launch_project_su(int nc, int64_t nlinks, const void* U, const void* g, void* F, hipStream_t st);
+
+// RHS-per-thread choice for a stencil (tunable; must divide nv).
+int choose_rb(dirac_op op, dirac_prec prec, int nc, int nv);
+
+// ---------------------------------------------------------------------------
+// Multi-RHS BLAS-1.  Rows of nv complex numbers, rhs fastest.  Reductions are two-pass
+// with a fixed number of blocks and a fixed summation order; `partial` must hold
+// reduce_partial_doubles(nv) doubles of device scratch.
+// ---------------------------------------------------------------------------
+constexpr int kReduceBlocks = 512;
+constexpr int kReduceThreads = 256;
+inline size_t reduce_partial_doubles(int nv) { return static_cast<size_t>(kReduceBlocks) * 2 * nv; }
+
+int blas_norm2(dirac_prec p, const void* x, int64_t nrows, int nv, double* partial, double* out, hipStream_t st);
+int blas_dot(dirac_prec px, const void* x, dirac_prec py, const void* y, int64_t nrows, int nv, double* partial,
+             double* out, hipStream_t st);
+// y += a x  (a: device, 2 nv doubles)
+int blas_caxpy(dirac_prec px, const void* x, dirac_prec py, void* y, const double* a, int64_t nrows, int nv,
+               hipStream_t st);
+// y = x + a y
+int blas_cxpay(dirac_prec px, const void* x, dirac_prec py, void* y, const double* a, int64_t nrows, int nv,
+               hipStream_t st);
+int blas_cast(dirac_prec px, const void* x, dirac_prec py, void* y, int64_t ncomplex, hipStream_t st);
+int blas_gamma5(dirac_op op, dirac_prec p, const void* x, void* y, int nc, int nv, const Geom& g, hipStream_t st);
+// y = x * s_i, s real per RHS (device, nv doubles)
+int blas_rscale(dirac_prec px, const void* x, dirac_prec py, void* y, const double* s, int64_t nrows, int nv,
+                hipStream_t st);
+
+// Fused solver kernels (see solvers.cpp for their role).
+// r -= alpha q ; out(rr) = ||r||^2   (alpha: device 2nv doubles; r, q same precision p)
+int fused_r_update(dirac_prec pr, void* r, dirac_prec pq, const void* q, const double* alpha, int64_t nrows, int nv,
+                   double* partial, double* rr, hipStream_t st);
+// x += alpha p ; p = r + beta p   (x precision px; r, p precision pp)
+int fused_xp_update(dirac_prec px, void* x, dirac_prec pp, void* p, dirac_prec prr, const void* r, const double* alpha,
+                    const double* beta, int64_t nrows, int nv, hipStream_t st);
+// y = b - y  (residual from A x stored in y)
+int blas_bminus(dirac_prec pb, const void* b, dirac_prec py, void* y, int64_t nrows, int nv, hipStream_t st);
+// r = b - q (all complex elements, any precisions)
+int blas_sub(dirac_prec pb, const void* b, dirac_prec pq, const void* q, dirac_prec pr, void* r, int64_t n,
+             hipStream_t st);
+// BiCGstab: x += alpha p + omega s ; r = s - omega t ; out = ||r||^2
+int fused_bicg_xr(dirac_prec p, void* x, const void* pv, const void* s, const void* t, void* r, const double* alpha,
+                  const double* omega, int64_t nrows, int nv, double* partial, double* rr, hipStream_t st);
+// BiCGstab: p = r + beta (p - omega v)
+int fused_bicg_p(dirac_prec p, void* pv, const void* r, const void* v, const double* beta, const double* omega,
+                 int64_t nrows, int nv, hipStream_t st);
+// BiCGstab: s = r - alpha v
+int fused_bicg_s(dirac_prec p, void* s, const void* r, const void* v, const double* alpha, int64_t nrows, int nv,
+                 hipStream_t st);
+
+}  // namespace dirac

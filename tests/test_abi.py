@@ -1,0 +1,122 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol of include/dirac.h, and
+rejects bad arguments before launching anything (no GPU is touched by these calls)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2112_14640_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dirac.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:int|size_t|double|const char\*)\s+(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_documented_calls():
+    names = _declared()
+    for required in ("dirac_apply", "dirac_apply_dagger", "cg_solve", "bicgstab_solve", "dirac_brillouin_links",
+                     "dirac_force", "dirac_solver_workspace_bytes", "dirac_error_string", "dirac_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(_declared()) <= set(L.SIGNATURES)
+
+
+def test_error_strings_and_flops():
+    lib = L.load()
+    for code in (L.OK, L.NOT_CONVERGED, L.EINVAL, L.EUNSUPPORTED, L.EHIP, L.EWORKSPACE, L.ENONFINITE, 99):
+        assert lib.dirac_error_string(code)
+    assert lib.dirac_version().startswith(b"libdirac")
+    # App. E counts for Nc = 3 (per site and RHS)
+    assert lib.dirac_flops_per_site(L.WILSON, 3) == 1368
+    assert lib.dirac_flops_per_site(L.BRILLOUIN, 3) == 30168
+    assert lib.dirac_flops_per_site(L.STAGGERED, 3) == 582
+
+
+def _dims(n=(4, 4, 4, 4), ap=1):
+    d = L.Dims()
+    for i, v in enumerate(n):
+        d.n[i] = v
+    d.antiperiodic_t = ap
+    return d
+
+
+FAKE_A, FAKE_B, FAKE_G = 0x10000000, 0x20000000, 0x30000000  # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("args,code", [
+    ((7, L.FP32, FAKE_G, FAKE_A, FAKE_B, 0.1, 3, 4), L.EINVAL),       # unknown operator
+    ((L.WILSON, 9, FAKE_G, FAKE_A, FAKE_B, 0.1, 3, 4), L.EINVAL),     # unknown precision
+    ((L.WILSON, L.FP32, None, FAKE_A, FAKE_B, 0.1, 3, 4), L.EINVAL),  # NULL gauge
+    ((L.WILSON, L.FP32, FAKE_G, FAKE_A, FAKE_A, 0.1, 3, 4), L.EINVAL),  # u == v
+    ((L.WILSON, L.FP32, FAKE_G, FAKE_A, FAKE_B, 0.1, 5, 4), L.EUNSUPPORTED),  # Nc = 5
+    ((L.WILSON, L.FP32, FAKE_G, FAKE_A, FAKE_B, 0.1, 3, 0), L.EINVAL),  # Nv = 0
+    ((L.WILSON, L.FP32, FAKE_G, FAKE_A, FAKE_B, 0.1, 3, 300), L.EINVAL),  # Nv too large
+    ((L.WILSON, L.FP32, FAKE_G, FAKE_A, FAKE_B, float("nan"), 3, 4), L.EINVAL),  # non-finite mass
+    ((L.WILSON, L.FP32, FAKE_G, FAKE_A + 4, FAKE_B, 0.1, 3, 4), L.EINVAL),  # misaligned
+])
+def test_apply_rejects_bad_arguments(args, code):
+    lib = L.load()
+    d = _dims()
+    assert lib.dirac_apply(*args, C.byref(d), None) == code
+    assert lib.dirac_last_error()
+
+
+def test_extent_rules():
+    lib = L.load()
+    d = _dims((4, 1, 4, 4))
+    assert lib.dirac_apply(L.WILSON, L.FP32, FAKE_G, FAKE_A, FAKE_B, 0.1, 3, 4, C.byref(d), None) == L.EINVAL
+    d = _dims((4, 3, 4, 4))
+    assert lib.dirac_apply(L.STAGGERED, L.FP32, FAKE_G, FAKE_A, FAKE_B, 0.1, 3, 4, C.byref(d), None) == L.EINVAL
+    assert lib.dirac_apply(L.WILSON, L.FP32, FAKE_G, FAKE_A, FAKE_B, 0.1, 3, 4, None, None) == L.EINVAL
+
+
+def test_solver_validation():
+    lib = L.load()
+    d = _dims()
+    info = L.SolveInfo()
+    # workspace query
+    n64 = lib.dirac_solver_workspace_bytes(L.WILSON, 0, L.FP64, L.FP64, 3, 12, C.byref(d))
+    nmix = lib.dirac_solver_workspace_bytes(L.WILSON, 0, L.FP64, L.BF16, 3, 12, C.byref(d))
+    assert n64 > 4 * 256 * 3 * 4 * 12 * 16 and nmix > 0
+    assert lib.dirac_solver_workspace_bytes(L.WILSON, 0, L.FP64, L.FP64, 3, 0, C.byref(d)) == 0
+    args = dict(op=L.WILSON, outer=L.FP64, inner=L.FP64, g=FAKE_G, gl=None, b=FAKE_A, x=FAKE_B, m=0.1, nc=3, nv=12,
+                tol=1e-10, maxit=10, ws=0x40000000, wsb=n64)
+
+    def call(**kw):
+        a = dict(args, **kw)
+        return lib.cg_solve(a["op"], a["outer"], a["inner"], a["g"], a["gl"], a["b"], a["x"], a["m"], a["nc"], a["nv"],
+                            C.byref(d), a["tol"], a["maxit"], a["ws"], a["wsb"], C.byref(info), None, None)
+
+    assert call(wsb=n64 - 1) == L.EWORKSPACE
+    assert call(tol=0.0) == L.EINVAL
+    assert call(maxit=-1) == L.EINVAL
+    assert call(x=FAKE_A) == L.EINVAL  # b and x alias
+    assert call(inner=L.FP32) == L.EINVAL  # mixed precision without low-precision links
+    assert call(outer=L.FP32, inner=L.BF16, gl=FAKE_G) == L.EUNSUPPORTED  # mixed needs an FP64 outer
+    assert lib.bicgstab_solve(L.STAGGERED, L.FP64, L.FP64, FAKE_G, None, FAKE_A, FAKE_B, 0.1, 3, 12, C.byref(d), 1e-8,
+                              10, 0x40000000, n64, None, None, None) == L.EUNSUPPORTED
+
+
+def test_blas_and_misc_validation():
+    lib = L.load()
+    assert lib.dirac_blas_workspace_bytes(12) > 0 and lib.dirac_blas_workspace_bytes(0) == 0
+    assert lib.dirac_norm2(L.FP32, FAKE_A, 100, 12, FAKE_B, FAKE_G, 8, None) == L.EWORKSPACE
+    assert lib.dirac_caxpy(L.FP32, FAKE_A, L.FP32, FAKE_A, FAKE_G, 100, 12, None) == L.EINVAL  # x and y alias
+    assert lib.dirac_force(L.BRILLOUIN, FAKE_G, FAKE_A, FAKE_B, 0x50000000, 1.0, 3, 2, C.byref(_dims()), None) \
+        == L.EUNSUPPORTED
+    assert lib.dirac_project_su(FAKE_G, FAKE_A, FAKE_B, 7, 10, None) == L.EUNSUPPORTED
+    assert lib.dirac_set_rhs_per_thread(L.BRILLOUIN, L.FP32, 4) == L.EUNSUPPORTED
+    assert lib.dirac_set_rhs_per_thread(L.WILSON, L.FP32, 3) == L.EINVAL
+    assert lib.dirac_set_rhs_per_thread(L.WILSON, L.FP32, 0) == L.OK

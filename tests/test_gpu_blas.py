@@ -1,0 +1,86 @@
+"""GPU parity of the multi-RHS BLAS-1 kernels (Sec. 3) against NumPy on the same stored values."""
+import numpy as np
+import pytest
+import torch
+
+import synthetic_inputs as si
+from paper_2112_14640_amd import dirac
+from tests.gpu_helpers import bf16_pairs_to_host, host, round_bf16, round_c64, to_bf16_pairs, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a, prec):
+    if prec == "fp64":
+        return to_dev(a), a
+    if prec == "fp32":
+        return to_dev(a, torch.complex64), round_c64(a)
+    return to_bf16_pairs(a), round_bf16(a)
+
+
+def _host(t, prec):
+    return bf16_pairs_to_host(t) if prec == "bf16" else host(t).astype(np.complex128)
+
+
+SHAPES = [(7, 1), (33, 5), (1000, 12), (40000, 12), (3, 256), (257, 24)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_norm2_and_dot(prec, shape):
+    rng = np.random.default_rng(1)
+    x = si.complex_gaussian(rng, shape)
+    y = si.complex_gaussian(rng, shape)
+    xd, xv = _dev(x, prec)
+    yd, yv = _dev(y, prec)
+    n = host(dirac.norm2(xd))
+    np.testing.assert_allclose(n, np.sum(np.abs(xv) ** 2, axis=0), rtol=1e-12)
+    d = host(dirac.dot(xd, yd))
+    np.testing.assert_allclose(d, np.sum(np.conj(xv) * yv, axis=0), rtol=1e-11, atol=1e-11 * np.sqrt(shape[0]))
+    # fixed summation order: bitwise reproducible
+    assert np.array_equal(host(dirac.norm2(xd)), n)
+
+
+@pytest.mark.parametrize("px,py", [("fp64", "fp64"), ("fp32", "fp32"), ("fp32", "fp64"), ("bf16", "fp32"),
+                                   ("fp64", "bf16")])
+def test_caxpy_cxpay(px, py):
+    rng = np.random.default_rng(2)
+    shape = (2049, 12)
+    x = si.complex_gaussian(rng, shape)
+    y = si.complex_gaussian(rng, shape)
+    a = si.complex_gaussian(rng, (12,))
+    xd, xv = _dev(x, px)
+    yd, yv = _dev(y, py)
+    dirac.caxpy(torch.from_numpy(a), xd, yd)
+    expect = yv + a * xv
+    tol = {"fp64": 1e-14, "fp32": 1e-6, "bf16": 8e-3}[py]
+    np.testing.assert_allclose(_host(yd, py), expect, rtol=0, atol=tol * 4)
+    yd2, yv2 = _dev(y, py)
+    dirac.cxpay(xd, torch.from_numpy(a), yd2)
+    np.testing.assert_allclose(_host(yd2, py), xv + a * yv2, rtol=0, atol=tol * 4)
+
+
+def test_cast_round_to_nearest_even():
+    rng = np.random.default_rng(3)
+    x = si.complex_gaussian(rng, (5000, 3)) * 10.0 ** rng.uniform(-20, 20, (5000, 3))
+    xd = to_dev(x)
+    x32 = dirac.cast(xd, "fp32")
+    assert np.array_equal(host(x32), x.astype(np.complex64))
+    xb = dirac.cast(x32, "bf16")
+    ref = torch.view_as_real(torch.from_numpy(x.astype(np.complex64))).to(torch.bfloat16)
+    assert torch.equal(xb.cpu().view(torch.int16), ref.view(torch.int16))
+    back = dirac.cast(xb, "fp64")
+    np.testing.assert_array_equal(host(back), round_bf16(x))
+
+
+def test_gamma5_and_epsilon():
+    rng = np.random.default_rng(4)
+    dims = (4, 2, 6, 4)
+    nx, ny, nz, nt = dims
+    psi = si.wilson_vector(rng, dims, 3, 5)
+    out = host(dirac.gamma5("wilson", to_dev(psi)))
+    np.testing.assert_array_equal(out, psi * np.array([1, 1, -1, -1])[:, None])
+    phi = si.staggered_vector(rng, dims, 3, 5)
+    t, z, y, x = np.meshgrid(np.arange(nt), np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    eps = np.where((x + y + z + t) % 2 == 0, 1.0, -1.0)[..., None, None]
+    np.testing.assert_array_equal(host(dirac.gamma5("staggered", to_dev(phi))), phi * eps)
