@@ -138,3 +138,70 @@ def config(name: str):
         "apply_48x96": dict(dims=(48, 48, 48, 96), nc=3, nv=12, mass=0.05, links="haar", spread=None, seed=0),
     }
     return dict(table[name])
+
+
+# ---------------------------------------------------------------------------
+# Device-side generators (torch) for lattices too large to draw on the host.
+# Same recipes as above, drawn from a seeded torch.Generator on the target device;
+# the random streams differ from the NumPy ones, so these feed benchmarks, not the
+# oracle comparisons.
+# ---------------------------------------------------------------------------
+def complex_gaussian_t(gen, shape, device, dtype=None):
+    import torch
+
+    dtype = dtype or torch.complex128
+    real = torch.float64 if dtype == torch.complex128 else torch.float32
+    g = torch.randn(tuple(shape) + (2,), generator=gen, device=device, dtype=real)
+    return torch.view_as_complex(g / 2 ** 0.5).to(dtype)
+
+
+def haar_su_n_t(gen, shape, nc, device, dtype=None):
+    """Haar SU(nc): Gram-Schmidt on the columns of a complex Gaussian matrix (the QR method with a
+    positive diagonal of R), then the determinant phase removed by det^(1/nc)."""
+    import torch
+
+    z = complex_gaussian_t(gen, tuple(shape) + (nc, nc), device, torch.complex128)
+    cols = []
+    for j in range(nc):
+        v = z[..., :, j]
+        for q in cols:
+            v = v - (torch.conj(q) * v).sum(-1, keepdim=True) * q
+        v = v / torch.linalg.vector_norm(v, dim=-1, keepdim=True)
+        cols.append(v)
+    q = torch.stack(cols, dim=-1)
+    det = _det_small(q)
+    q = q / (det ** (1.0 / nc))[..., None, None]
+    return q.to(dtype or torch.complex128).contiguous()
+
+
+def _det_small(m):
+    """Determinant of (..., n, n) matrices by cofactor expansion along the first row (n <= 4)."""
+    n = m.shape[-1]
+    if n == 1:
+        return m[..., 0, 0]
+    det = 0
+    for j in range(n):
+        minor = m[..., 1:, [k for k in range(n) if k != j]]
+        det = det + (-1) ** j * m[..., 0, j] * _det_small(minor)
+    return det
+
+
+def near_identity_su_n_t(gen, shape, nc, spread, device, dtype=None):
+    """exp(i spread H), H traceless hermitian Gaussian (as near_identity_su_n); the exponential by a
+    Taylor series after scaling by 2^-6 and six squarings (converged to double precision)."""
+    import torch
+
+    a = complex_gaussian_t(gen, tuple(shape) + (nc, nc), device, torch.complex128)
+    h = 0.5 * (a + torch.conj(a.transpose(-1, -2)))
+    tr = torch.diagonal(h, dim1=-2, dim2=-1).real.sum(-1) / nc
+    h = h - tr[..., None, None] * torch.eye(nc, dtype=h.dtype, device=device)
+    x = (1j * spread / 64.0) * h
+    eye = torch.eye(nc, dtype=h.dtype, device=device).expand_as(x)
+    term = eye.clone()
+    u = eye.clone()
+    for k in range(1, 16):
+        term = torch.matmul(term, x.contiguous()) / k
+        u = u + term
+    for _ in range(6):
+        u = torch.matmul(u, u.contiguous())
+    return u.to(dtype or torch.complex128).contiguous()
