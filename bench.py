@@ -233,6 +233,9 @@ def main():
     ap.add_argument("--sets", type=int, default=4)
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 512 MiB device copy (outside the timed steps) whose HBM counters "
+                         "scale the PMC byte counts of the stencil kernels")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported (the multi-GPU "
@@ -245,6 +248,14 @@ def main():
     from paper_2112_14640_amd import dirac
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(512 * 2 ** 20 // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] calibration copies done: 5 x 512 MiB read + 512 MiB write")
+        del src, dst
     res = run_applies(args, torch, dirac, si)
     cg = None if args.no_cg else run_cg(torch, dirac, si)
     cpu = None if args.no_cpu else run_cpu_baseline(si)

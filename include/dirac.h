@@ -202,10 +202,12 @@ int bicgstab_solve(dirac_op op, dirac_prec outer, dirac_prec inner, const void* 
                    int maxit, void* workspace, size_t ws_bytes, dirac_solve_info* info,
                    const dirac_solve_opts* opts, void* stream);
 
-/* Launch-shape knob: right-hand sides handled by one thread of the stencil kernels for
- * (op, prec).  rb = 0 restores the automatic choice; 1, 2 or 4 (Brillouin: 1 or 2) force it
- * whenever it divides nv.  Results do not depend on it.  Process-wide, not thread-safe. */
-int dirac_set_rhs_per_thread(dirac_op op, dirac_prec prec, int rb);
+/* Launch-shape knob for the stencil kernels of (op, prec): rb = right-hand sides handled by
+ * one thread (0 automatic; 1, 2 or 4, Brillouin 1 or 2; used whenever it divides nv);
+ * variant = 0 automatic, 1 direct global loads (hops unrolled), 2 LDS-staged site tiles,
+ * 3 direct global loads with one hop direction per loop iteration (Wilson, staggered).
+ * Results agree to rounding whatever the shape.  Process-wide, not thread-safe. */
+int dirac_set_launch_shape(dirac_op op, dirac_prec prec, int rb, int variant);
 
 /* Flop count per site and RHS of one apply, App. E convention (daggers count the same). */
 double dirac_flops_per_site(dirac_op op, int nc);

@@ -70,7 +70,7 @@ SIGNATURES = {
                       C.POINTER(SolveOpts), _vp]),
     "bicgstab_solve": (_i, [_i, _i, _i, _vp, _vp, _vp, _vp, _d, _i, _i, _dims, _d, _i, _vp, _sz,
                             C.POINTER(SolveInfo), C.POINTER(SolveOpts), _vp]),
-    "dirac_set_rhs_per_thread": (_i, [_i, _i, _i]),
+    "dirac_set_launch_shape": (_i, [_i, _i, _i, _i]),
     "dirac_flops_per_site": (_d, [_i, _i]),
     "dirac_error_string": (C.c_char_p, [_i]),
     "dirac_last_error": (C.c_char_p, []),

@@ -21,8 +21,9 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb) {
 
 bool aligned(const void* p, size_t a) { return reinterpret_cast<uintptr_t>(p) % a == 0; }
 
-// Tuned RHS-per-thread overrides, [op][prec]; 0 = automatic.
+// Launch-shape overrides, [op][prec]; 0 = automatic.
 int g_rb_override[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+int g_variant_override[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
 
 int check_common(dirac_op op, dirac_prec prec, int nc, int nv, const dirac_dims* dims, Geom& g) {
     if (op < DIRAC_WILSON || op > DIRAC_STAGGERED) return fail(DIRAC_EINVAL, "unknown operator");
@@ -39,6 +40,7 @@ int check_common(dirac_op op, dirac_prec prec, int nc, int nv, const dirac_dims*
     g.nz = dims->n[2];
     g.nt = dims->n[3];
     g.vol = static_cast<int64_t>(g.nx) * g.ny * g.nz * g.nt;
+    if (g.vol >= (int64_t(1) << 31)) return fail(DIRAC_EINVAL, "lattice volume must be below 2^31 sites");
     g.apbc = dims->antiperiodic_t ? 1 : 0;
     return DIRAC_OK;
 }
@@ -63,7 +65,7 @@ int stencil(dirac_op op, dirac_prec prec, const void* gauge, const void* u, void
         !aligned(gauge, gauge_complex_bytes(prec)))
         return fail(DIRAC_EINVAL, "misaligned pointer");
     if (!std::isfinite(mass)) return fail(DIRAC_EINVAL, "mass is not finite");
-    StencilArgs a{prec, nc, nv, choose_rb(op, prec, nc, nv), dag, mass, g, gauge, u, v};
+    StencilArgs a{prec, nc, nv, choose_rb(op, prec, nc, nv), choose_variant(op, prec), dag, mass, g, gauge, u, v};
     hipStream_t st = as_stream(stream);
     switch (op) {
         case DIRAC_WILSON: rc = launch_wilson(a, st); break;
@@ -89,20 +91,30 @@ int check_hip(hipError_t e, const char* what) {
     return DIRAC_EHIP;
 }
 
+// Default launch shapes, chosen by timing every shape at 16^3 x 32, Nc = 3, Nv = 12 on MI355X:
+//   Wilson   FP32: 2 RHS/thread, hops unrolled      FP64, BF16: 1 RHS/thread, one hop per iteration
+//   staggered: 2 RHS/thread, hops unrolled          Brillouin: 1 RHS/thread
+// A shape that does not divide nv falls back to fewer RHS per thread.
 int choose_rb(dirac_op op, dirac_prec prec, int nc, int nv) {
     const int o = g_rb_override[op][prec];
     if (o > 0 && nv % o == 0) return o;
     (void)nc;
     switch (op) {
         case DIRAC_WILSON:
-            if (prec == DIRAC_FP64) return 1;
-            return nv % 2 == 0 ? 2 : 1;
+            return (prec == DIRAC_FP32 && nv % 2 == 0) ? 2 : 1;
         case DIRAC_STAGGERED:
-            if (prec != DIRAC_FP64 && nv % 4 == 0) return 4;
             return nv % 2 == 0 ? 2 : 1;
         case DIRAC_BRILLOUIN:
             return 1;
     }
+    return 1;
+}
+
+// 1 = direct loads with hops unrolled, 2 = LDS-staged tiles, 3 = direct loads, one hop per iteration
+int choose_variant(dirac_op op, dirac_prec prec) {
+    const int o = g_variant_override[op][prec];
+    if (o > 0) return o;
+    if (op == DIRAC_WILSON && prec != DIRAC_FP32) return 3;
     return 1;
 }
 
@@ -332,13 +344,15 @@ int bicgstab_solve(dirac_op op, dirac_prec outer, dirac_prec inner, const void* 
                  info, opts, stream);
 }
 
-int dirac_set_rhs_per_thread(dirac_op op, dirac_prec prec, int rb) {
+int dirac_set_launch_shape(dirac_op op, dirac_prec prec, int rb, int variant) {
     if (op < DIRAC_WILSON || op > DIRAC_STAGGERED || prec < DIRAC_FP64 || prec > DIRAC_BF16)
         return fail(DIRAC_EINVAL, "unknown operator or precision");
     const int maxrb = op == DIRAC_BRILLOUIN ? 2 : 4;
     if (rb != 0 && rb != 1 && rb != 2 && rb != 4) return fail(DIRAC_EINVAL, "rb must be 0, 1, 2 or 4");
     if (rb > maxrb) return fail(DIRAC_EUNSUPPORTED, "rb not instantiated for this operator");
+    if (variant < 0 || variant > 3) return fail(DIRAC_EINVAL, "variant must be 0..3");
     g_rb_override[op][prec] = rb;
+    g_variant_override[op][prec] = variant;
     return DIRAC_OK;
 }
 

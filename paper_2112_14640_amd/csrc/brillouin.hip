@@ -113,14 +113,15 @@ template <int NC, int RB, bool DAG, class P>
 __global__ __launch_bounds__(256) void brillouin_kernel(const typename P::G* __restrict__ W,
                                                          const typename P::S* __restrict__ in,
                                                          typename P::S* __restrict__ out, typename P::R diag, Geom g,
-                                                         int nv) {
+                                                         int nv, SiteOrder order) {
     using R = typename P::R;
     using S = typename P::S;
     const int nrg = nv / RB;
     const int64_t gid = logical_block() * blockDim.x + threadIdx.x;
     if (gid >= g.vol * nrg) return;
-    const int64_t site = gid / nrg;
-    const int r0 = static_cast<int>(gid - site * nrg) * RB;
+    const int64_t idx = gid / nrg;
+    const int r0 = static_cast<int>(gid - idx * nrg) * RB;
+    const int64_t site = ordered_site(idx, order, g);
     const Coord c = site_coord(site, g);
     const int64_t vs = static_cast<int64_t>(NC) * 4 * nv;
 
@@ -133,17 +134,26 @@ __global__ __launch_bounds__(256) void brillouin_kernel(const typename P::G* __r
 #pragma unroll
             for (int s = 0; s < 4; ++s) acc[k][a][s] = cscale(diag, io<R, S>::ld(centre + (a * 4 + s) * nv + k));
 
+    // neighbour offsets along each axis for steps -1, 0, +1 (with the periodic wrap) and the
+    // fermion sign of the t steps; per direction the neighbour is site + four offsets
+    // (site offsets fit in 32 bits: the library limits the volume to < 2^31 sites)
+    const int sy = g.nx, sz = g.nx * g.ny, stt = sz * g.nz;
+    const int ox[3] = {c.x == 0 ? g.nx - 1 : -1, 0, c.x == g.nx - 1 ? 1 - g.nx : 1};
+    const int oy[3] = {(c.y == 0 ? g.ny - 1 : -1) * sy, 0, (c.y == g.ny - 1 ? 1 - g.ny : 1) * sy};
+    const int oz[3] = {(c.z == 0 ? g.nz - 1 : -1) * sz, 0, (c.z == g.nz - 1 ? 1 - g.nz : 1) * sz};
+    const int ot[3] = {(c.t == 0 ? g.nt - 1 : -1) * stt, 0, (c.t == g.nt - 1 ? 1 - g.nt : 1) * stt};
+    const R sgn_t[3] = {(g.apbc && c.t == 0) ? R(-1) : R(1), R(1), (g.apbc && c.t == g.nt - 1) ? R(-1) : R(1)};
+
     for (int dir = 0; dir < 81; ++dir) {
         if (dir == 40) continue;
-        const int dx = dir % 3 - 1, dy = (dir / 3) % 3 - 1, dz = (dir / 9) % 3 - 1, dt = dir / 27 - 1;
-        const int kh = (dx != 0) + (dy != 0) + (dz != 0) + (dt != 0);
+        // wave-uniform direction data
+        const int ix = dir % 3, iy = (dir / 3) % 3, iz = (dir / 9) % 3, it = dir / 27;
+        const int kh = (ix != 1) + (iy != 1) + (iz != 1) + (it != 1);
         const R rho = static_cast<R>(DAG ? -c_rho[kh] : c_rho[kh]);
-        const R q1 = rho * dx, q2 = rho * dy, q3 = rho * dz, q4 = rho * dt;
+        const R q1 = rho * (ix - 1), q2 = rho * (iy - 1), q3 = rho * (iz - 1), q4 = rho * (it - 1);
         const R lh = static_cast<R>(c_halflam[kh]);
-        const int tt = c.t + dt;
-        const int64_t nb = site_index(wrap(c.x + dx, g.nx), wrap(c.y + dy, g.ny), wrap(c.z + dz, g.nz),
-                                      wrap(tt, g.nt), g);
-        const R bsign = (g.apbc && (tt < 0 || tt >= g.nt)) ? R(-1) : R(1);
+        const int64_t nb = site + (ox[ix] + oy[iy] + oz[iz] + ot[it]);
+        const R bsign = sgn_t[it];
 
         cx<R> l[NC][NC];
         if (dir < 40) {
@@ -174,20 +184,42 @@ __global__ __launch_bounds__(256) void brillouin_kernel(const typename P::G* __r
                 for (int b = 0; b < NC; ++b)
 #pragma unroll
                     for (int s = 0; s < 4; ++s) cfma(ch[s], l[a][b], p[b][s]);
-                // spin mixing: rows 0,1 get -lh ch + B ch_{2,3}; rows 2,3 get -lh ch + B^+ ch_{0,1}
                 cx<R>* o = acc[k][a];
-                // (q4 - i q3) ch2 + (-q2 - i q1) ch3
-                o[0].re += -lh * ch[0].re + q4 * ch[2].re + q3 * ch[2].im - q2 * ch[3].re + q1 * ch[3].im;
-                o[0].im += -lh * ch[0].im + q4 * ch[2].im - q3 * ch[2].re - q2 * ch[3].im - q1 * ch[3].re;
-                // (q2 - i q1) ch2 + (q4 + i q3) ch3
-                o[1].re += -lh * ch[1].re + q2 * ch[2].re + q1 * ch[2].im + q4 * ch[3].re - q3 * ch[3].im;
-                o[1].im += -lh * ch[1].im + q2 * ch[2].im - q1 * ch[2].re + q4 * ch[3].im + q3 * ch[3].re;
-                // (q4 + i q3) ch0 + (q2 + i q1) ch1
-                o[2].re += -lh * ch[2].re + q4 * ch[0].re - q3 * ch[0].im + q2 * ch[1].re - q1 * ch[1].im;
-                o[2].im += -lh * ch[2].im + q4 * ch[0].im + q3 * ch[0].re + q2 * ch[1].im + q1 * ch[1].re;
-                // (-q2 + i q1) ch0 + (q4 - i q3) ch1
-                o[3].re += -lh * ch[3].re - q2 * ch[0].re - q1 * ch[0].im + q4 * ch[1].re + q3 * ch[1].im;
-                o[3].im += -lh * ch[3].im - q2 * ch[0].im + q1 * ch[0].re + q4 * ch[1].im - q3 * ch[1].re;
+                // -lambda_k/2 (spin diagonal)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    o[s].re -= lh * ch[s].re;
+                    o[s].im -= lh * ch[s].im;
+                }
+                // rho_k sum_mu d_mu g_mu in the chiral basis, one displacement component at a time:
+                //   g_4: rows (0,1,2,3) <- (2,3,0,1)
+                //   g_3: rows <- (-i 2, +i 3, +i 0, -i 1)
+                //   g_2: rows <- (-3, +2, +1, -0)
+                //   g_1: rows <- (-i 3, -i 2, +i 1, +i 0)
+                if (it != 1) {
+                    o[0].re += q4 * ch[2].re; o[0].im += q4 * ch[2].im;
+                    o[1].re += q4 * ch[3].re; o[1].im += q4 * ch[3].im;
+                    o[2].re += q4 * ch[0].re; o[2].im += q4 * ch[0].im;
+                    o[3].re += q4 * ch[1].re; o[3].im += q4 * ch[1].im;
+                }
+                if (iz != 1) {
+                    o[0].re += q3 * ch[2].im; o[0].im -= q3 * ch[2].re;
+                    o[1].re -= q3 * ch[3].im; o[1].im += q3 * ch[3].re;
+                    o[2].re -= q3 * ch[0].im; o[2].im += q3 * ch[0].re;
+                    o[3].re += q3 * ch[1].im; o[3].im -= q3 * ch[1].re;
+                }
+                if (iy != 1) {
+                    o[0].re -= q2 * ch[3].re; o[0].im -= q2 * ch[3].im;
+                    o[1].re += q2 * ch[2].re; o[1].im += q2 * ch[2].im;
+                    o[2].re += q2 * ch[1].re; o[2].im += q2 * ch[1].im;
+                    o[3].re -= q2 * ch[0].re; o[3].im -= q2 * ch[0].im;
+                }
+                if (ix != 1) {
+                    o[0].re += q1 * ch[3].im; o[0].im -= q1 * ch[3].re;
+                    o[1].re += q1 * ch[2].im; o[1].im -= q1 * ch[2].re;
+                    o[2].re -= q1 * ch[1].im; o[2].im += q1 * ch[1].re;
+                    o[3].re -= q1 * ch[0].im; o[3].im += q1 * ch[0].re;
+                }
             }
         }
     }
@@ -212,10 +244,11 @@ void launch_rb(const StencilArgs& a, hipStream_t st) {
     auto in = static_cast<const typename P::S*>(a.in);
     auto out = static_cast<typename P::S*>(a.out);
     if (a.dagger)
-        hipLaunchKernelGGL((brillouin_kernel<NC, RB, true, P>), grid, dim3(block), 0, st, W, in, out, diag, a.g, a.nv);
+        hipLaunchKernelGGL((brillouin_kernel<NC, RB, true, P>), grid, dim3(block), 0, st, W, in, out, diag, a.g, a.nv,
+                           make_site_order(a.g));
     else
         hipLaunchKernelGGL((brillouin_kernel<NC, RB, false, P>), grid, dim3(block), 0, st, W, in, out, diag, a.g,
-                           a.nv);
+                           a.nv, make_site_order(a.g));
 }
 
 template <int NC, class P>

@@ -198,6 +198,56 @@ __device__ __forceinline__ int wrap(int v, int n) {
     return v < 0 ? v + n : (v >= n ? v - n : v);
 }
 
+// Site traversal order of the stencil kernels.  The lattice is cut into xyz bricks of
+// bx*by*bz sites; each brick column (the brick at every t) is walked with t slowest and x
+// fastest inside the brick.  Consecutive threads therefore read neighbouring sites, the +-t
+// neighbours of a brick slice are one brick slice (bx*by*bz sites) away in traversal order
+// (well inside one XCD's L2, unlike a whole t-slice of the lattice), and rows of bx sites
+// stay contiguous in memory.  Memory layout is unchanged; only the site each thread owns.
+struct SiteOrder {
+    int bx, by, bz;    // brick extents (divide nx, ny, nz)
+    int nbx, nby;      // bricks along x and y
+    int bslice;        // bx*by*bz
+    int64_t column;    // bslice * nt sites per brick column
+};
+
+__device__ __forceinline__ int64_t ordered_site(int64_t i, const SiteOrder& o, const Geom& g) {
+    const int64_t col = i / o.column;
+    const int64_t r = i - col * o.column;
+    const int t = static_cast<int>(r / o.bslice);
+    int q = static_cast<int>(r - static_cast<int64_t>(t) * o.bslice);
+    const int bxy = o.bx * o.by;
+    const int lz = q / bxy;
+    q -= lz * bxy;
+    const int ly = q / o.bx;
+    const int lx = q - ly * o.bx;
+    const int cbx = static_cast<int>(col % o.nbx);
+    const int64_t c2 = col / o.nbx;
+    const int cby = static_cast<int>(c2 % o.nby);
+    const int cbz = static_cast<int>(c2 / o.nby);
+    return site_index(cbx * o.bx + lx, cby * o.by + ly, cbz * o.bz + lz, t, g);
+}
+
+// Brick extent along one axis: the whole axis when short, else 8 (or a divisor near it).
+inline int brick_extent(int n) {
+    if (n <= 12) return n;
+    for (int b : {8, 12, 10, 6, 16, 4, 2})
+        if (n % b == 0) return b;
+    return n;
+}
+
+inline SiteOrder make_site_order(const Geom& g) {
+    SiteOrder o;
+    o.bx = brick_extent(g.nx);
+    o.by = brick_extent(g.ny);
+    o.bz = brick_extent(g.nz);
+    o.nbx = g.nx / o.bx;
+    o.nby = g.ny / o.by;
+    o.bslice = o.bx * o.by * o.bz;
+    o.column = static_cast<int64_t>(o.bslice) * g.nt;
+    return o;
+}
+
 // XCD-aware block order: the hardware hands consecutive workgroups to the eight
 // XCDs round-robin; remapping gives each XCD a contiguous range of logical blocks,
 // so neighbouring sites (shared stencil reads) land in the same L2.  The launch

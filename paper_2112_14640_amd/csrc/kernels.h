@@ -9,7 +9,8 @@ struct StencilArgs {
     dirac_prec prec;
     int nc;
     int nv;
-    int rb;  // right-hand sides per thread (divides nv)
+    int rb;       // right-hand sides per thread (divides nv)
+    int variant;  // 0: automatic (LDS-staged tile when it fits), 1: direct global loads
     bool dagger;
     double mass;
     Geom g;
@@ -27,8 +28,9 @@ int launch_force(dirac_op op, int nc, int nv, const Geom& g, const void* U, cons
                  void* gout, double coeff, hipStream_t st);
 int launch_project_su(int nc, int64_t nlinks, const void* U, const void* g, void* F, hipStream_t st);
 
-// RHS-per-thread choice for a stencil (tunable; must divide nv).
+// RHS-per-thread choice for a stencil (tunable; must divide nv) and kernel variant.
 int choose_rb(dirac_op op, dirac_prec prec, int nc, int nv);
+int choose_variant(dirac_op op, dirac_prec prec);
 
 // ---------------------------------------------------------------------------
 // Multi-RHS BLAS-1.  Rows of nv complex numbers, rhs fastest.  Reductions are two-pass

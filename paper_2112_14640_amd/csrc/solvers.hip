@@ -53,7 +53,8 @@ struct OpCtx {
 size_t vec_bytes(const OpCtx& o, dirac_prec p) { return o.ncomplex() * complex_bytes(p); }
 
 int apply_op(const OpCtx& o, dirac_prec p, const void* gauge, const void* in, void* out, bool dag, hipStream_t st) {
-    StencilArgs a{p, o.nc, o.nv, choose_rb(o.op, p, o.nc, o.nv), dag, o.mass, o.g, gauge, in, out};
+    StencilArgs a{p, o.nc, o.nv, choose_rb(o.op, p, o.nc, o.nv), choose_variant(o.op, p), dag, o.mass, o.g, gauge, in,
+                  out};
     switch (o.op) {
         case DIRAC_WILSON: return launch_wilson(a, st);
         case DIRAC_BRILLOUIN: return launch_brillouin(a, st);

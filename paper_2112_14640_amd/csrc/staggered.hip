@@ -5,8 +5,11 @@
 //
 // eta_mu(n) = (-1)^(x_0 + ... + x_{mu-1}) on 0-based coordinates.  One thread owns a site
 // and RB consecutive right-hand sides, so each link is loaded once per RB columns.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
+#include "tile.h"
 
 namespace dirac {
 
@@ -40,17 +43,18 @@ __device__ __forceinline__ void stag_hop(cx<typename P::R> (&acc)[RB][NC], const
     }
 }
 
-template <int NC, int RB, bool DAG, class P>
+template <int NC, int RB, bool DAG, class P, bool LOOP>
 __global__ __launch_bounds__(256) void staggered_kernel(const typename P::G* __restrict__ U,
                                                          const typename P::S* __restrict__ in,
                                                          typename P::S* __restrict__ out, typename P::R mass, Geom g,
-                                                         int nv) {
+                                                         int nv, SiteOrder order) {
     using R = typename P::R;
     const int nrg = nv / RB;
     const int64_t gid = logical_block() * blockDim.x + threadIdx.x;
     if (gid >= g.vol * nrg) return;
-    const int64_t site = gid / nrg;
-    const int r0 = static_cast<int>(gid - site * nrg) * RB;
+    const int64_t idx = gid / nrg;
+    const int r0 = static_cast<int>(gid - idx * nrg) * RB;
+    const int64_t site = ordered_site(idx, order, g);
     const Coord c = site_coord(site, g);
     const int64_t vs = static_cast<int64_t>(NC) * nv;
 
@@ -66,7 +70,8 @@ __global__ __launch_bounds__(256) void staggered_kernel(const typename P::G* __r
     const int64_t stride[4] = {1, g.nx, static_cast<int64_t>(g.nx) * g.ny, static_cast<int64_t>(g.nx) * g.ny * g.nz};
     const int coord[4] = {c.x, c.y, c.z, c.t};
     const int ext[4] = {g.nx, g.ny, g.nz, g.nt};
-#pragma unroll
+    // LOOP: one direction per iteration (bounded live registers); else fully unrolled
+#pragma unroll(LOOP ? 1 : 4)
     for (int mu = 0; mu < 4; ++mu) {
         const R eta = par[mu] ? -half : half;
         const int64_t fwd = site + (coord[mu] == ext[mu] - 1 ? (1 - ext[mu]) * stride[mu] : stride[mu]);
@@ -87,9 +92,161 @@ __global__ __launch_bounds__(256) void staggered_kernel(const typename P::G* __r
         for (int a = 0; a < NC; ++a) io<R, typename P::S>::st(o + a * nv + k, acc[k][a]);
 }
 
+// LDS-staged variant (see tile.h): neighbour blocks and links of a tile of S sites pass
+// through LDS so that every global load and store instruction is contiguous.
+template <int NC, int RB, bool DAG, class P, typename Unit>
+__global__ __launch_bounds__(512) void staggered_lds_kernel(const typename P::G* __restrict__ U,
+                                                             const typename P::S* __restrict__ in,
+                                                             typename P::S* __restrict__ out, typename P::R mass,
+                                                             Geom g, int nv, TileGeom tg) {
+    using R = typename P::R;
+    using S = typename P::S;
+    using G = typename P::G;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int St = tg.S;
+    constexpr int L = NC * NC;
+    int* nb = reinterpret_cast<int*>(smem);
+    size_t off = (static_cast<size_t>(kHopSlots) * St * sizeof(int) + 15) / 16 * 16;
+    G* lf = reinterpret_cast<G*>(smem + off);
+    off += (static_cast<size_t>(St) * 4 * L * sizeof(G) + 15) / 16 * 16;
+    G* lb = reinterpret_cast<G*>(smem + off);
+    off += (static_cast<size_t>(St) * L * sizeof(G) + 15) / 16 * 16;
+    Unit* tile = reinterpret_cast<Unit*>(smem + off);
+
+    const int64_t s0 = logical_block() * St;
+    if (s0 >= g.vol) return;
+    const int nsites = static_cast<int>(g.vol - s0 < St ? g.vol - s0 : St);
+    tile_neighbours(nb, s0, St, g);
+    {
+        const size_t bytes = static_cast<size_t>(nsites) * 4 * L * sizeof(G);
+        copy_in(reinterpret_cast<uint4*>(lf), reinterpret_cast<const uint4*>(U + s0 * 4 * L),
+                static_cast<uint32_t>(bytes / 16));
+    }
+    __syncthreads();  // the neighbour table is read by every thread below
+    const uint32_t tid = threadIdx.x;
+    const uint32_t j = fast_div(tid, tg.magic_nrg);
+    const int rg = static_cast<int>(tid - j * tg.nrg);
+    const bool active = j < static_cast<uint32_t>(nsites);
+    const int r0 = rg * RB;
+    int par[4] = {0, 0, 0, 0};
+    int ct = 0;
+    if (active) {
+        const Coord c = site_coord(s0 + j, g);
+        par[1] = c.x & 1;
+        par[2] = (c.x + c.y) & 1;
+        par[3] = (c.x + c.y + c.z) & 1;
+        ct = c.t;
+    }
+    const S* mine = reinterpret_cast<const S*>(tile + j * (tg.units + 1)) + r0;
+    const Unit* src = reinterpret_cast<const Unit*>(in);
+
+    cx<R> acc[RB][NC];
+    tile_gather(tile, src, nb, tg);
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int k = 0; k < RB; ++k)
+#pragma unroll
+            for (int a = 0; a < NC; ++a) acc[k][a] = cscale(mass, io<R, S>::ld(mine + a * nv + k));
+    }
+    const R half = DAG ? R(-0.5) : R(0.5);
+    auto direction = [&](auto mu_c) {
+        constexpr int MU = decltype(mu_c)::value;
+        const R eta = par[MU] ? -half : half;
+        R sf = eta, sb = -eta;
+        if (MU == 3 && g.apbc) {
+            if (ct == g.nt - 1) sf = -sf;
+            if (ct == 0) sb = -sb;
+        }
+        __syncthreads();
+        tile_gather(tile, src, nb + (1 + 2 * MU) * St, tg);
+        __syncthreads();
+        if (active) stag_hop<NC, RB, false, P>(acc, lf + (j * 4 + MU) * L, mine, nv, sf);
+        __syncthreads();
+        tile_gather(tile, src, nb + (2 + 2 * MU) * St, tg);
+        for (uint32_t u = tid; u < static_cast<uint32_t>(St * L); u += blockDim.x) {
+            const uint32_t jj = u / L;
+            const uint32_t e = u - jj * L;
+            lb[u] = U[(static_cast<int64_t>(nb[(2 + 2 * MU) * St + jj]) * 4 + MU) * L + e];
+        }
+        __syncthreads();
+        if (active) stag_hop<NC, RB, true, P>(acc, lb + j * L, mine, nv, sb);
+    };
+    direction(std::integral_constant<int, 0>{});
+    direction(std::integral_constant<int, 1>{});
+    direction(std::integral_constant<int, 2>{});
+    direction(std::integral_constant<int, 3>{});
+    __syncthreads();
+    if (active) {
+        S* o = const_cast<S*>(mine);
+#pragma unroll
+        for (int k = 0; k < RB; ++k)
+#pragma unroll
+            for (int a = 0; a < NC; ++a) io<R, S>::st(o + a * nv + k, acc[k][a]);
+    }
+    __syncthreads();
+    tile_scatter_out(reinterpret_cast<Unit*>(out) + s0 * tg.units, tile, nsites, tg);
+}
+
+template <int NC, int RB, class P, typename Unit>
+void launch_lds_unit(const StencilArgs& a, hipStream_t st, int units) {
+    using R = typename P::R;
+    using S = typename P::S;
+    using G = typename P::G;
+    const int nrg = a.nv / RB;
+    auto lds_of = [&](int s) { return lds_bytes(s, 4 * NC * NC * sizeof(G), NC * NC * sizeof(G), units, sizeof(Unit)); };
+    const int St = choose_tile_sites(nrg, lds_of);
+    TileGeom tg{St, nrg, units, div_magic(units), div_magic(nrg)};
+    const int threads = (St * nrg + 63) / 64 * 64;
+    const dim3 grid(static_cast<unsigned>(grid_blocks_x8(a.g.vol, St)));
+    auto U = static_cast<const G*>(a.gauge);
+    auto in = static_cast<const S*>(a.in);
+    auto out = static_cast<S*>(a.out);
+    const R m = static_cast<R>(a.mass);
+    if (a.dagger)
+        hipLaunchKernelGGL((staggered_lds_kernel<NC, RB, true, P, Unit>), grid, dim3(threads), lds_of(St), st, U, in,
+                           out, m, a.g, a.nv, tg);
+    else
+        hipLaunchKernelGGL((staggered_lds_kernel<NC, RB, false, P, Unit>), grid, dim3(threads), lds_of(St), st, U, in,
+                           out, m, a.g, a.nv, tg);
+}
+
+template <int NC, int RB, class P>
+bool launch_lds(const StencilArgs& a, hipStream_t st) {
+    using S = typename P::S;
+    using G = typename P::G;
+    const size_t block_bytes = static_cast<size_t>(NC) * a.nv * sizeof(S);
+    if (!tile_aligned(a)) return false;
+    const int nrg = a.nv / RB;
+    if (block_bytes % 16 == 0) {
+        const int units = static_cast<int>(block_bytes / 16);
+        if (!choose_tile_sites(nrg, [&](int s) {
+                return lds_bytes(s, 4 * NC * NC * sizeof(G), NC * NC * sizeof(G), units, 16);
+            }))
+            return false;
+        launch_lds_unit<NC, RB, P, uint4>(a, st, units);
+    } else if (block_bytes % 8 == 0) {
+        const int units = static_cast<int>(block_bytes / 8);
+        if (!choose_tile_sites(nrg, [&](int s) {
+                return lds_bytes(s, 4 * NC * NC * sizeof(G), NC * NC * sizeof(G), units, 8);
+            }))
+            return false;
+        launch_lds_unit<NC, RB, P, uint2>(a, st, units);
+    } else {
+        const int units = static_cast<int>(block_bytes / 4);
+        if (!choose_tile_sites(nrg, [&](int s) {
+                return lds_bytes(s, 4 * NC * NC * sizeof(G), NC * NC * sizeof(G), units, 4);
+            }))
+            return false;
+        launch_lds_unit<NC, RB, P, uint32_t>(a, st, units);
+    }
+    return true;
+}
+
 template <int NC, int RB, class P>
 void launch_rb(const StencilArgs& a, hipStream_t st) {
     using R = typename P::R;
+    if (use_lds_variant(a, false) && launch_lds<NC, RB, P>(a, st)) return;
     const int block = 256;
     const int64_t threads = a.g.vol * (a.nv / RB);
     const dim3 grid(static_cast<unsigned>(grid_blocks_x8(threads, block)));
@@ -97,10 +254,22 @@ void launch_rb(const StencilArgs& a, hipStream_t st) {
     auto in = static_cast<const typename P::S*>(a.in);
     auto out = static_cast<typename P::S*>(a.out);
     const R m = static_cast<R>(a.mass);
-    if (a.dagger)
-        hipLaunchKernelGGL((staggered_kernel<NC, RB, true, P>), grid, dim3(block), 0, st, U, in, out, m, a.g, a.nv);
-    else
-        hipLaunchKernelGGL((staggered_kernel<NC, RB, false, P>), grid, dim3(block), 0, st, U, in, out, m, a.g, a.nv);
+    const SiteOrder ord = make_site_order(a.g);
+    if (a.variant == 3) {
+        if (a.dagger)
+            hipLaunchKernelGGL((staggered_kernel<NC, RB, true, P, true>), grid, dim3(block), 0, st, U, in, out, m, a.g,
+                               a.nv, ord);
+        else
+            hipLaunchKernelGGL((staggered_kernel<NC, RB, false, P, true>), grid, dim3(block), 0, st, U, in, out, m,
+                               a.g, a.nv, ord);
+    } else {
+        if (a.dagger)
+            hipLaunchKernelGGL((staggered_kernel<NC, RB, true, P, false>), grid, dim3(block), 0, st, U, in, out, m,
+                               a.g, a.nv, ord);
+        else
+            hipLaunchKernelGGL((staggered_kernel<NC, RB, false, P, false>), grid, dim3(block), 0, st, U, in, out, m,
+                               a.g, a.nv, ord);
+    }
 }
 
 template <int NC, class P>

@@ -9,8 +9,11 @@
 // One thread owns one site and RB consecutive right-hand sides; every output element is
 // written once (no atomics).  Fermion fields pick up -1 on t-wrapping hops when
 // antiperiodic in t.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
+#include "tile.h"
 
 namespace dirac {
 
@@ -136,6 +139,76 @@ __device__ __forceinline__ void hop(cx<typename P::R> (&acc)[RB][NC][4], const t
     }
 }
 
+// Direction-generic hop (runtime mu and projector sign, wave-uniform).  With P = 1 + sig g_mu
+// in the chiral basis the half spinor is h0 = p0 + c0 p_A, h1 = p1 + c1 p_B and the full spinor
+// is rebuilt as (h0, h1, e2 h_C, e3 h_D), where every c, e is one of +-1, +-i:
+//   mu=0: A,B = 3,2  c0,c1 = -sig i, -sig i   C,D = 1,0  e2,e3 = sig i, sig i
+//   mu=1: A,B = 3,2  c0,c1 = -sig, +sig       C,D = 1,0  e2,e3 = sig, -sig
+//   mu=2: A,B = 2,3  c0,c1 = -sig i, +sig i   C,D = 0,1  e2,e3 = sig i, -sig i
+//   mu=3: A,B = 2,3  c0,c1 = +sig, +sig       C,D = 0,1  e2,e3 = sig, sig
+struct UnitC {
+    int re, im;
+};
+template <typename R>
+__device__ __forceinline__ cx<R> umul(UnitC u, cx<R> x) {
+    // (u.re + i u.im)(x.re + i x.im), u one of +-1, +-i
+    return {R(u.re) * x.re - R(u.im) * x.im, R(u.re) * x.im + R(u.im) * x.re};
+}
+
+template <int NC, int RB, class P>
+__device__ __forceinline__ void hop_rt(cx<typename P::R> (&acc)[RB][NC][4], const typename P::G* __restrict__ link,
+                                       bool adj, const typename P::S* __restrict__ nb, int nv, typename P::R scale,
+                                       int mu, int sig) {
+    using R = typename P::R;
+    const bool lo = mu < 2;
+    UnitC c0, c1, e2, e3;
+    switch (mu) {
+        case 0: c0 = {0, -sig}; c1 = {0, -sig}; e2 = {0, sig}; e3 = {0, sig}; break;
+        case 1: c0 = {-sig, 0}; c1 = {sig, 0}; e2 = {sig, 0}; e3 = {-sig, 0}; break;
+        case 2: c0 = {0, -sig}; c1 = {0, sig}; e2 = {0, sig}; e3 = {0, -sig}; break;
+        default: c0 = {sig, 0}; c1 = {sig, 0}; e2 = {sig, 0}; e3 = {sig, 0}; break;
+    }
+    cx<R> l[NC][NC];
+    if (adj) {
+#pragma unroll
+        for (int a = 0; a < NC; ++a)
+#pragma unroll
+            for (int b = 0; b < NC; ++b) l[b][a] = cconj(io<R, typename P::G>::ld(link + a * NC + b));
+    } else {
+#pragma unroll
+        for (int a = 0; a < NC; ++a)
+#pragma unroll
+            for (int b = 0; b < NC; ++b) l[a][b] = io<R, typename P::G>::ld(link + a * NC + b);
+    }
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {
+        cx<R> h0[NC], h1[NC];
+#pragma unroll
+        for (int b = 0; b < NC; ++b) {
+            cx<R> p[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) p[s] = io<R, typename P::S>::ld(nb + (b * 4 + s) * nv + k);
+            const cx<R> pa = lo ? p[3] : p[2];
+            const cx<R> pb = lo ? p[2] : p[3];
+            h0[b] = cscale(scale, cadd(p[0], umul(c0, pa)));
+            h1[b] = cscale(scale, cadd(p[1], umul(c1, pb)));
+        }
+#pragma unroll
+        for (int a = 0; a < NC; ++a) {
+            cx<R> x0{R(0), R(0)}, x1{R(0), R(0)};
+#pragma unroll
+            for (int b = 0; b < NC; ++b) {
+                cfma(x0, l[a][b], h0[b]);
+                cfma(x1, l[a][b], h1[b]);
+            }
+            acc[k][a][0] = cadd(acc[k][a][0], x0);
+            acc[k][a][1] = cadd(acc[k][a][1], x1);
+            acc[k][a][2] = cadd(acc[k][a][2], umul(e2, lo ? x1 : x0));
+            acc[k][a][3] = cadd(acc[k][a][3], umul(e3, lo ? x0 : x1));
+        }
+    }
+}
+
 template <int NC, int RB, int MU, bool DAG, class P>
 __device__ __forceinline__ void both_hops(cx<typename P::R> (&acc)[RB][NC][4], const typename P::G* __restrict__ U,
                                           const typename P::S* __restrict__ in, int64_t site, const Coord& c,
@@ -169,17 +242,18 @@ __device__ __forceinline__ void both_hops(cx<typename P::R> (&acc)[RB][NC][4], c
     hop<NC, RB, MU, -SF, true, P>(acc, U + (bwd * 4 + MU) * NC * NC, in + bwd * vs + r0, nv, sb);
 }
 
-template <int NC, int RB, bool DAG, class P>
+template <int NC, int RB, bool DAG, class P, bool LOOP>
 __global__ __launch_bounds__(256) void wilson_kernel(const typename P::G* __restrict__ U,
                                                       const typename P::S* __restrict__ in,
                                                       typename P::S* __restrict__ out, typename P::R diag, Geom g,
-                                                      int nv) {
+                                                      int nv, SiteOrder order) {
     using R = typename P::R;
     const int nrg = nv / RB;
     const int64_t gid = logical_block() * blockDim.x + threadIdx.x;
     if (gid >= g.vol * nrg) return;
-    const int64_t site = gid / nrg;
-    const int r0 = static_cast<int>(gid - site * nrg) * RB;
+    const int64_t idx = gid / nrg;
+    const int r0 = static_cast<int>(gid - idx * nrg) * RB;
+    const int64_t site = ordered_site(idx, order, g);
     const Coord c = site_coord(site, g);
     const int64_t vs = static_cast<int64_t>(NC) * 4 * nv;
 
@@ -193,10 +267,39 @@ __global__ __launch_bounds__(256) void wilson_kernel(const typename P::G* __rest
             for (int s = 0; s < 4; ++s)
                 acc[k][a][s] = cscale(diag, io<R, typename P::S>::ld(centre + (a * 4 + s) * nv + k));
 
-    both_hops<NC, RB, 0, DAG, P>(acc, U, in, site, c, g, nv, r0);
-    both_hops<NC, RB, 1, DAG, P>(acc, U, in, site, c, g, nv, r0);
-    both_hops<NC, RB, 2, DAG, P>(acc, U, in, site, c, g, nv, r0);
-    both_hops<NC, RB, 3, DAG, P>(acc, U, in, site, c, g, nv, r0);
+    if constexpr (LOOP) {
+        // one hop per iteration: only its loads are live, which keeps the register count (and
+        // so the number of waves per SIMD hiding memory latency) moderate
+        const int co[4] = {c.x, c.y, c.z, c.t};
+        const int ext[4] = {g.nx, g.ny, g.nz, g.nt};
+#pragma nounroll
+        for (int d = 0; d < 8; ++d) {
+            const int mu = d >> 1;
+            const bool back = d & 1;
+            const int64_t stride = mu == 0 ? 1 : (mu == 1 ? g.nx : (mu == 2 ? static_cast<int64_t>(g.nx) * g.ny
+                                                                             : static_cast<int64_t>(g.nx) * g.ny * g.nz));
+            const int cm = mu == 0 ? co[0] : (mu == 1 ? co[1] : (mu == 2 ? co[2] : co[3]));
+            const int em = mu == 0 ? ext[0] : (mu == 1 ? ext[1] : (mu == 2 ? ext[2] : ext[3]));
+            int64_t nbs;
+            typename P::R scale = typename P::R(-0.5);
+            if (!back) {
+                nbs = site + (cm == em - 1 ? (1 - em) * stride : stride);
+                if (mu == 3 && g.apbc && cm == em - 1) scale = typename P::R(0.5);
+            } else {
+                nbs = site - (cm == 0 ? (1 - em) * stride : stride);
+                if (mu == 3 && g.apbc && cm == 0) scale = typename P::R(0.5);
+            }
+            // D: forward (1 - g_mu), backward (1 + g_mu); the adjoint swaps them
+            const int sig = (back != DAG) ? 1 : -1;
+            const typename P::G* link = U + ((back ? nbs : site) * 4 + mu) * NC * NC;
+            hop_rt<NC, RB, P>(acc, link, back, in + nbs * vs + r0, nv, scale, mu, sig);
+        }
+    } else {
+        both_hops<NC, RB, 0, DAG, P>(acc, U, in, site, c, g, nv, r0);
+        both_hops<NC, RB, 1, DAG, P>(acc, U, in, site, c, g, nv, r0);
+        both_hops<NC, RB, 2, DAG, P>(acc, U, in, site, c, g, nv, r0);
+        both_hops<NC, RB, 3, DAG, P>(acc, U, in, site, c, g, nv, r0);
+    }
 
     typename P::S* o = out + site * vs + r0;
 #pragma unroll
@@ -207,9 +310,134 @@ __global__ __launch_bounds__(256) void wilson_kernel(const typename P::G* __rest
             for (int s = 0; s < 4; ++s) io<R, typename P::S>::st(o + (a * 4 + s) * nv + k, acc[k][a][s]);
 }
 
+// LDS-staged variant: the work-group owns S consecutive sites; per hop direction the S
+// neighbour blocks are gathered into LDS with contiguous loads, the tile's forward links
+// live in LDS for the whole kernel and the backward links of the current direction are
+// gathered next to the spinors; the output tile leaves through LDS as contiguous stores.
+template <int NC, int RB, bool DAG, class P, typename Unit>
+__global__ __launch_bounds__(512) void wilson_lds_kernel(const typename P::G* __restrict__ U,
+                                                          const typename P::S* __restrict__ in,
+                                                          typename P::S* __restrict__ out, typename P::R diag, Geom g,
+                                                          int nv, TileGeom tg) {
+    using R = typename P::R;
+    using S = typename P::S;
+    using G = typename P::G;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int St = tg.S;
+    constexpr int L = NC * NC;
+    int* nb = reinterpret_cast<int*>(smem);
+    size_t off = (static_cast<size_t>(kHopSlots) * St * sizeof(int) + 15) / 16 * 16;
+    G* lf = reinterpret_cast<G*>(smem + off);
+    off += (static_cast<size_t>(St) * 4 * L * sizeof(G) + 15) / 16 * 16;
+    G* lb = reinterpret_cast<G*>(smem + off);
+    off += (static_cast<size_t>(St) * L * sizeof(G) + 15) / 16 * 16;
+    Unit* tile = reinterpret_cast<Unit*>(smem + off);
+
+    const int64_t s0 = logical_block() * St;
+    if (s0 >= g.vol) return;
+    const int nsites = static_cast<int>(g.vol - s0 < St ? g.vol - s0 : St);
+    tile_neighbours(nb, s0, St, g);
+    {
+        const size_t bytes = static_cast<size_t>(nsites) * 4 * L * sizeof(G);
+        copy_in(reinterpret_cast<uint4*>(lf), reinterpret_cast<const uint4*>(U + s0 * 4 * L),
+                static_cast<uint32_t>(bytes / 16));
+    }
+    __syncthreads();  // the neighbour table is read by every thread below
+    const uint32_t tid = threadIdx.x;
+    const uint32_t j = fast_div(tid, tg.magic_nrg);
+    const int rg = static_cast<int>(tid - j * tg.nrg);
+    const bool active = j < static_cast<uint32_t>(nsites);
+    const int r0 = rg * RB;
+    int ct = 0;
+    if (active) ct = site_coord(s0 + j, g).t;
+    const S* mine = reinterpret_cast<const S*>(tile + j * (tg.units + 1)) + r0;
+    const Unit* src = reinterpret_cast<const Unit*>(in);
+
+    cx<R> acc[RB][NC][4];
+    tile_gather(tile, src, nb, tg);
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int k = 0; k < RB; ++k)
+#pragma unroll
+            for (int a = 0; a < NC; ++a)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) acc[k][a][s] = cscale(diag, io<R, S>::ld(mine + (a * 4 + s) * nv + k));
+    }
+    constexpr int SF = DAG ? 1 : -1;  // forward projector 1 + SF g_mu
+    auto direction = [&](auto mu_c) {
+        constexpr int MU = decltype(mu_c)::value;
+        R sf = R(-0.5), sb = R(-0.5);
+        if (MU == 3 && g.apbc) {
+            if (ct == g.nt - 1) sf = R(0.5);
+            if (ct == 0) sb = R(0.5);
+        }
+        __syncthreads();
+        tile_gather(tile, src, nb + (1 + 2 * MU) * St, tg);
+        __syncthreads();
+        if (active) hop<NC, RB, MU, SF, false, P>(acc, lf + (j * 4 + MU) * L, mine, nv, sf);
+        __syncthreads();
+        tile_gather(tile, src, nb + (2 + 2 * MU) * St, tg);
+        for (uint32_t u = tid; u < static_cast<uint32_t>(St * L); u += blockDim.x) {
+            const uint32_t jj = u / L;
+            const uint32_t e = u - jj * L;
+            lb[u] = U[(static_cast<int64_t>(nb[(2 + 2 * MU) * St + jj]) * 4 + MU) * L + e];
+        }
+        __syncthreads();
+        if (active) hop<NC, RB, MU, -SF, true, P>(acc, lb + j * L, mine, nv, sb);
+    };
+    direction(std::integral_constant<int, 0>{});
+    direction(std::integral_constant<int, 1>{});
+    direction(std::integral_constant<int, 2>{});
+    direction(std::integral_constant<int, 3>{});
+    __syncthreads();
+    if (active) {
+        S* o = const_cast<S*>(mine);
+#pragma unroll
+        for (int k = 0; k < RB; ++k)
+#pragma unroll
+            for (int a = 0; a < NC; ++a)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) io<R, S>::st(o + (a * 4 + s) * nv + k, acc[k][a][s]);
+    }
+    __syncthreads();
+    tile_scatter_out(reinterpret_cast<Unit*>(out) + s0 * tg.units, tile, nsites, tg);
+}
+
+template <int NC, int RB, class P>
+bool launch_lds(const StencilArgs& a, hipStream_t st) {
+    using R = typename P::R;
+    using S = typename P::S;
+    using G = typename P::G;
+    const int nrg = a.nv / RB;
+    const size_t block_bytes = static_cast<size_t>(NC) * 4 * a.nv * sizeof(S);
+    if (block_bytes % 16 != 0 || !tile_aligned(a)) return false;
+    const int units = static_cast<int>(block_bytes / 16);
+    const int St = choose_tile_sites(nrg, [&](int s) {
+        return lds_bytes(s, 4 * NC * NC * sizeof(G), NC * NC * sizeof(G), units, 16);
+    });
+    if (St == 0) return false;
+    TileGeom tg{St, nrg, units, div_magic(units), div_magic(nrg)};
+    const int threads = (St * nrg + 63) / 64 * 64;
+    const size_t lds = lds_bytes(St, 4 * NC * NC * sizeof(G), NC * NC * sizeof(G), units, 16);
+    const dim3 grid(static_cast<unsigned>(grid_blocks_x8(a.g.vol, St)));
+    const R diag = static_cast<R>(4.0 + a.mass);
+    auto U = static_cast<const G*>(a.gauge);
+    auto in = static_cast<const S*>(a.in);
+    auto out = static_cast<S*>(a.out);
+    if (a.dagger)
+        hipLaunchKernelGGL((wilson_lds_kernel<NC, RB, true, P, uint4>), grid, dim3(threads), lds, st, U, in, out, diag,
+                           a.g, a.nv, tg);
+    else
+        hipLaunchKernelGGL((wilson_lds_kernel<NC, RB, false, P, uint4>), grid, dim3(threads), lds, st, U, in, out,
+                           diag, a.g, a.nv, tg);
+    return true;
+}
+
 template <int NC, int RB, class P>
 void launch_rb(const StencilArgs& a, hipStream_t st) {
     using R = typename P::R;
+    if (use_lds_variant(a) && launch_lds<NC, RB, P>(a, st)) return;
     const int block = 256;
     const int64_t threads = a.g.vol * (a.nv / RB);
     const dim3 grid(static_cast<unsigned>(grid_blocks_x8(threads, block)));
@@ -217,10 +445,22 @@ void launch_rb(const StencilArgs& a, hipStream_t st) {
     auto U = static_cast<const typename P::G*>(a.gauge);
     auto in = static_cast<const typename P::S*>(a.in);
     auto out = static_cast<typename P::S*>(a.out);
-    if (a.dagger)
-        hipLaunchKernelGGL((wilson_kernel<NC, RB, true, P>), grid, dim3(block), 0, st, U, in, out, diag, a.g, a.nv);
-    else
-        hipLaunchKernelGGL((wilson_kernel<NC, RB, false, P>), grid, dim3(block), 0, st, U, in, out, diag, a.g, a.nv);
+    const SiteOrder ord = make_site_order(a.g);
+    if (a.variant == 3) {
+        if (a.dagger)
+            hipLaunchKernelGGL((wilson_kernel<NC, RB, true, P, true>), grid, dim3(block), 0, st, U, in, out, diag, a.g,
+                               a.nv, ord);
+        else
+            hipLaunchKernelGGL((wilson_kernel<NC, RB, false, P, true>), grid, dim3(block), 0, st, U, in, out, diag,
+                               a.g, a.nv, ord);
+    } else {
+        if (a.dagger)
+            hipLaunchKernelGGL((wilson_kernel<NC, RB, true, P, false>), grid, dim3(block), 0, st, U, in, out, diag,
+                               a.g, a.nv, ord);
+        else
+            hipLaunchKernelGGL((wilson_kernel<NC, RB, false, P, false>), grid, dim3(block), 0, st, U, in, out, diag,
+                               a.g, a.nv, ord);
+    }
 }
 
 template <int NC, class P>

@@ -395,8 +395,9 @@ def flops_per_site(op, nc: int) -> float:
     return L.load().dirac_flops_per_site(_op(op), nc)
 
 
-def set_rhs_per_thread(op, prec, rb: int):
-    """Launch-shape knob of the stencil kernels (0 = automatic)."""
+def set_launch_shape(op, prec, rb: int = 0, variant: int = 0):
+    """Launch-shape knob of the stencil kernels: RHS per thread (0 = automatic) and variant
+    (0 = automatic, 1 = direct global loads, 2 = LDS-staged site tiles)."""
     if isinstance(prec, str):
         prec = {"fp64": L.FP64, "fp32": L.FP32, "bf16": L.BF16}[prec]
-    L.check(L.load().dirac_set_rhs_per_thread(_op(op), prec, rb), "set_rhs_per_thread")
+    L.check(L.load().dirac_set_launch_shape(_op(op), prec, rb, variant), "set_launch_shape")

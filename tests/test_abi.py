@@ -117,6 +117,6 @@ def test_blas_and_misc_validation():
     assert lib.dirac_force(L.BRILLOUIN, FAKE_G, FAKE_A, FAKE_B, 0x50000000, 1.0, 3, 2, C.byref(_dims()), None) \
         == L.EUNSUPPORTED
     assert lib.dirac_project_su(FAKE_G, FAKE_A, FAKE_B, 7, 10, None) == L.EUNSUPPORTED
-    assert lib.dirac_set_rhs_per_thread(L.BRILLOUIN, L.FP32, 4) == L.EUNSUPPORTED
-    assert lib.dirac_set_rhs_per_thread(L.WILSON, L.FP32, 3) == L.EINVAL
-    assert lib.dirac_set_rhs_per_thread(L.WILSON, L.FP32, 0) == L.OK
+    assert lib.dirac_set_launch_shape(L.BRILLOUIN, L.FP32, 4, 0) == L.EUNSUPPORTED
+    assert lib.dirac_set_launch_shape(L.WILSON, L.FP32, 3, 0) == L.EINVAL
+    assert lib.dirac_set_launch_shape(L.WILSON, L.FP32, 0, 0) == L.OK

@@ -184,18 +184,20 @@ def test_free_field_plane_wave_16x32():
     assert col_rel_err(host(v), expect) < 1e-12
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 @pytest.mark.parametrize("rb", [1, 2, 4])
 @pytest.mark.parametrize("op", ["wilson", "staggered", "brillouin"])
-def test_rhs_per_thread_variants_agree(op, rb):
-    if op == "brillouin" and rb == 4:
-        pytest.skip("Brillouin instantiates 1 or 2 right-hand sides per thread")
-    dims, nc, nv = (4, 4, 4, 6), 3, 12
+def test_launch_shapes_agree(op, rb, variant):
+    """Every launch shape (RHS per thread, LDS-staged or direct) gives the oracle's result."""
+    if op == "brillouin" and (rb == 4 or variant >= 2):
+        pytest.skip("Brillouin instantiates 1 or 2 right-hand sides per thread and has no tiled variant")
+    dims, nc, nv = (6, 4, 4, 6), 3, 12
     gauge, u = _inputs(op, dims, nc, nv, seed=9)
     try:
-        dirac.set_rhs_per_thread(op, "fp32", rb)
+        dirac.set_launch_shape(op, "fp32", rb, variant)
         v, g_in, u_in = _run(op, "fp32", gauge, u, 0.1, True, False)
     finally:
-        dirac.set_rhs_per_thread(op, "fp32", 0)
+        dirac.set_launch_shape(op, "fp32", 0, 0)
     ref = ORACLE[(op, False)](g_in, u_in, 0.1, True)
     assert col_rel_err(v, ref) < 1e-5
 
