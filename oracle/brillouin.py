@@ -30,7 +30,7 @@ import itertools
 import numpy as np
 
 from .gamma import GAMMA, IDENTITY4
-from .lattice import all_sites, bc_sign, dims_of_gauge, flat_index, site_field, unit
+from .lattice import all_sites, bc_sign, dims_of_gauge, flat_index, rows, site_field, unit
 
 RHO = np.array([0.0, 64.0, 16.0, 4.0, 1.0]) / 432.0  # index k = 1..4 (index 0 unused)
 LAMBDA = np.array([-240.0, 8.0, 4.0, 2.0, 1.0]) / 64.0  # index k = 0..4
@@ -63,8 +63,8 @@ def _step_link(us, coords, step, dims):
     """Link for one unit step starting at each site: V_mu(x) for +mu, V_mu(x-mu)^dagger for -mu."""
     mu = int(np.flatnonzero(step)[0])
     if step[mu] > 0:
-        return us[flat_index(coords, dims), mu]
-    back = us[flat_index(coords - unit(mu), dims), mu]
+        return rows(us, (flat_index(coords, dims), mu))
+    back = rows(us, (flat_index(coords - unit(mu), dims), mu))
     return np.conj(np.swapaxes(back, -1, -2))
 
 
@@ -113,9 +113,9 @@ def link_from_stored(W40, coords, dir_index, dims):
     """W_d(n) at the given sites from the 40 stored directions (Tab. off-axis relation)."""
     ws = site_field(W40)
     if dir_index < CENTER:
-        return ws[flat_index(coords, dims), dir_index]
+        return rows(ws, (flat_index(coords, dims), dir_index))
     d = direction(dir_index)
-    w = ws[flat_index(coords + d, dims), 80 - dir_index]
+    w = rows(ws, (flat_index(coords + d, dims), 80 - dir_index))
     return np.conj(np.swapaxes(w, -1, -2))
 
 
@@ -127,20 +127,27 @@ def spin_factor(d, dagger=False) -> np.ndarray:
     return sgn * RHO[k] * der - 0.5 * LAMBDA[k] * IDENTITY4
 
 
-def _apply(W40, psi, mass, antiperiodic_t, sites, dagger):
-    nt, nz, ny, nx = W40.shape[:4]
-    dims = (nx, ny, nz, nt)
-    coords = all_sites(dims) if sites is None else np.asarray(sites)
+def _apply_with(link, psi, mass, antiperiodic_t, coords, dims, dagger):
+    """D_B (or D_B^dagger) at the given sites; link(dir) returns W_dir at those sites, shape (S, Nc, Nc)."""
     ps = site_field(psi)
-    out = (mass - 0.5 * LAMBDA[0]) * ps[flat_index(coords, dims)]
+    out = (mass - 0.5 * LAMBDA[0]) * rows(ps, flat_index(coords, dims))
     for dir_index in range(81):
         if dir_index == CENTER:
             continue
         d = direction(dir_index)
-        w = link_from_stored(W40, coords, dir_index, dims)
+        w = link(dir_index)
         b = bc_sign(coords, d, dims, antiperiodic_t)[:, None, None, None]
-        col = np.einsum("kab,kbsr->kasr", w, ps[flat_index(coords + d, dims)]) * b
+        col = np.einsum("kab,kbsr->kasr", w, rows(ps, flat_index(coords + d, dims))) * b
         out = out + np.einsum("st,katr->kasr", spin_factor(d, dagger), col)
+    return out
+
+
+def _apply(W40, psi, mass, antiperiodic_t, sites, dagger):
+    nt, nz, ny, nx = W40.shape[:4]
+    dims = (nx, ny, nz, nt)
+    coords = all_sites(dims) if sites is None else np.asarray(sites)
+    out = _apply_with(lambda k: link_from_stored(W40, coords, k, dims), psi, mass, antiperiodic_t, coords, dims,
+                      dagger)
     if sites is None:
         return out.reshape(psi.shape)
     return out
@@ -154,6 +161,15 @@ def brillouin_apply(W40, psi, mass, antiperiodic_t=True, sites=None):
 def brillouin_apply_dagger(W40, psi, mass, antiperiodic_t=True, sites=None):
     """v = D_B^dagger psi (rho part negated, see module docstring)."""
     return _apply(W40, psi, mass, antiperiodic_t, sites, dagger=True)
+
+
+def brillouin_apply_sites(W81, psi, mass, sites, antiperiodic_t=True, dagger=False):
+    """D_B psi (or D_B^dagger psi) at the given sites from all 81 links there: W81[k, dir] = W_dir(sites[k])
+    (as returned by ``brillouin_links_all(V, sites)``).  Avoids the full stored-link array on large lattices."""
+    coords = np.asarray(sites)
+    nt, nz, ny, nx = psi.shape[:4]
+    return _apply_with(lambda k: np.asarray(W81[:, k], dtype=np.complex128), psi, mass, antiperiodic_t, coords,
+                       (nx, ny, nz, nt), dagger)
 
 
 def free_brillouin_symbol(p, mass):

@@ -33,8 +33,8 @@ def wilson_force(U, psi, chi, antiperiodic_t=True):
     """g = d Re(psi^dagger D_W chi) / dU, shape of U."""
     dims = dims_of_gauge(U)
     coords = all_sites(dims)
-    ps = site_field(psi)
-    cs = site_field(chi)
+    ps = site_field(np.asarray(psi, dtype=np.complex128))
+    cs = site_field(np.asarray(chi, dtype=np.complex128))
     g = np.zeros(site_field(U).shape, dtype=np.complex128)
     for mu in range(4):
         e = unit(mu)
@@ -52,8 +52,8 @@ def staggered_force(U, psi, chi, antiperiodic_t=True):
     """g = d Re(psi^dagger D_S chi) / dU, shape of U."""
     dims = dims_of_gauge(U)
     coords = all_sites(dims)
-    ps = site_field(psi)
-    cs = site_field(chi)
+    ps = site_field(np.asarray(psi, dtype=np.complex128))
+    cs = site_field(np.asarray(chi, dtype=np.complex128))
     g = np.zeros(site_field(U).shape, dtype=np.complex128)
     for mu in range(4):
         e = unit(mu)

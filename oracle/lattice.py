@@ -36,6 +36,11 @@ def site_field(f: np.ndarray) -> np.ndarray:
     return f.reshape((-1,) + f.shape[4:])
 
 
+def rows(field_sites: np.ndarray, index) -> np.ndarray:
+    """Rows of a [site, ...] field as complex128, whatever the storage type (all arithmetic is FP64)."""
+    return np.asarray(field_sites[index], dtype=np.complex128)
+
+
 def bc_sign(coords: np.ndarray, disp, dims, antiperiodic_t: bool) -> np.ndarray:
     """Fermion boundary sign b(n, d): -1 iff antiperiodic in t and t + d_t leaves [0, Nt-1]."""
     nt = dims[3]

@@ -12,7 +12,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .lattice import all_sites, bc_sign, dims_of_gauge, eta, flat_index, site_field, unit
+from .lattice import all_sites, bc_sign, dims_of_gauge, eta, flat_index, rows, site_field, unit
 
 
 def _hop(U, phi, coords, dims, antiperiodic_t):
@@ -26,8 +26,8 @@ def _hop(U, phi, coords, dims, antiperiodic_t):
         bwd = flat_index(coords - e, dims)
         bf = bc_sign(coords, e, dims, antiperiodic_t)[:, None, None]
         bb = bc_sign(coords, -e, dims, antiperiodic_t)[:, None, None]
-        up = np.einsum("kab,kbr->kar", us[n, mu], ps[fwd]) * bf
-        dn = np.einsum("kba,kbr->kar", np.conj(us[bwd, mu]), ps[bwd]) * bb
+        up = np.einsum("kab,kbr->kar", rows(us, (n, mu)), rows(ps, fwd)) * bf
+        dn = np.einsum("kba,kbr->kar", np.conj(rows(us, (bwd, mu))), rows(ps, bwd)) * bb
         h = h + 0.5 * eta(coords, mu)[:, None, None] * (up - dn)
     return h
 
@@ -37,7 +37,7 @@ def staggered_apply(U, phi, mass, antiperiodic_t=True, sites=None):
     dims = dims_of_gauge(U)
     coords = all_sites(dims) if sites is None else np.asarray(sites)
     ps = site_field(phi)
-    out = mass * ps[flat_index(coords, dims)] + _hop(U, phi, coords, dims, antiperiodic_t)
+    out = mass * rows(ps, flat_index(coords, dims)) + _hop(U, phi, coords, dims, antiperiodic_t)
     return out.reshape(phi.shape) if sites is None else out
 
 
@@ -46,5 +46,5 @@ def staggered_apply_dagger(U, phi, mass, antiperiodic_t=True, sites=None):
     dims = dims_of_gauge(U)
     coords = all_sites(dims) if sites is None else np.asarray(sites)
     ps = site_field(phi)
-    out = mass * ps[flat_index(coords, dims)] - _hop(U, phi, coords, dims, antiperiodic_t)
+    out = mass * rows(ps, flat_index(coords, dims)) - _hop(U, phi, coords, dims, antiperiodic_t)
     return out.reshape(phi.shape) if sites is None else out

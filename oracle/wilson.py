@@ -19,7 +19,7 @@ from __future__ import annotations
 import numpy as np
 
 from .gamma import GAMMA, IDENTITY4
-from .lattice import all_sites, bc_sign, dims_of_gauge, flat_index, site_field, unit
+from .lattice import all_sites, bc_sign, dims_of_gauge, flat_index, rows, site_field, unit
 
 
 def _hop_terms(U, psi, coords, dims, antiperiodic_t):
@@ -33,9 +33,9 @@ def _hop_terms(U, psi, coords, dims, antiperiodic_t):
         bwd = flat_index(coords - e, dims)
         bf = bc_sign(coords, e, dims, antiperiodic_t)[:, None, None, None]
         bb = bc_sign(coords, -e, dims, antiperiodic_t)[:, None, None, None]
-        up = np.einsum("kab,kbsr->kasr", us[n, mu], ps[fwd]) * bf
+        up = np.einsum("kab,kbsr->kasr", rows(us, (n, mu)), rows(ps, fwd)) * bf
         # (U^dagger)[a, b] = conj(U[b, a])
-        dn = np.einsum("kba,kbsr->kasr", np.conj(us[bwd, mu]), ps[bwd]) * bb
+        dn = np.einsum("kba,kbsr->kasr", np.conj(rows(us, (bwd, mu))), rows(ps, bwd)) * bb
         yield mu, up, dn
 
 
@@ -59,7 +59,7 @@ def wilson_apply(U, psi, mass, antiperiodic_t=True, sites=None):
     dims = dims_of_gauge(U)
     coords = all_sites(dims) if sites is None else np.asarray(sites)
     ps = site_field(psi)
-    out = (4.0 + mass) * ps[flat_index(coords, dims)]
+    out = (4.0 + mass) * rows(ps, flat_index(coords, dims))
     for mu, up, dn in _hop_terms(U, psi, coords, dims, antiperiodic_t):
         out = out + 0.5 * _spin(GAMMA[mu] - IDENTITY4, up) - 0.5 * _spin(GAMMA[mu] + IDENTITY4, dn)
     return _finish(out, psi, sites)
@@ -70,7 +70,7 @@ def wilson_apply_dagger(U, psi, mass, antiperiodic_t=True, sites=None):
     dims = dims_of_gauge(U)
     coords = all_sites(dims) if sites is None else np.asarray(sites)
     ps = site_field(psi)
-    out = (4.0 + mass) * ps[flat_index(coords, dims)]
+    out = (4.0 + mass) * rows(ps, flat_index(coords, dims))
     for mu, up, dn in _hop_terms(U, psi, coords, dims, antiperiodic_t):
         out = out - 0.5 * _spin(GAMMA[mu] + IDENTITY4, up) + 0.5 * _spin(GAMMA[mu] - IDENTITY4, dn)
     return _finish(out, psi, sites)

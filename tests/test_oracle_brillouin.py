@@ -6,9 +6,9 @@ import numpy as np
 import pytest
 
 import synthetic_inputs as si
-from oracle.brillouin import (CENTER, LAMBDA, RHO, brillouin_apply, brillouin_apply_dagger, brillouin_links,
-                              brillouin_links_all, direction, direction_index, free_brillouin_symbol, hops,
-                              link_from_stored)
+from oracle.brillouin import (CENTER, LAMBDA, RHO, brillouin_apply, brillouin_apply_dagger, brillouin_apply_sites,
+                              brillouin_links, brillouin_links_all, direction, direction_index, free_brillouin_symbol,
+                              hops, link_from_stored)
 from oracle.dense import brillouin_dense
 from oracle.gamma import GAMMA, GAMMA5
 from oracle.lattice import all_sites, flat_index, site_field
@@ -231,3 +231,23 @@ def test_random_links_stencil_matches_dense_for_arbitrary_w():
     psi = si.wilson_vector(rng, dims, nc, 2)
     d = brillouin_dense(wall, dims, 0.07, True)
     assert rel_err(_cols(brillouin_apply(w40, psi, 0.07)), d @ _cols(psi)) < 1e-13
+
+
+def test_apply_from_links_at_sites_and_fp32_storage():
+    """The sampled-site form (81 links per site from the path averages, no stored array) gives the
+    stored-link apply; complex64 storage is evaluated in FP64 (same values as its complex128 copy)."""
+    dims, nc = (4, 2, 2, 4), 3
+    rng = np.random.default_rng(18)
+    V = si.gauge_field(rng, dims, nc, "haar")
+    psi = si.wilson_vector(rng, dims, nc, 2)
+    sites = np.array([[0, 0, 0, 0], [3, 1, 1, 3], [2, 0, 1, 1]])
+    w81 = brillouin_links_all(V, sites=sites)
+    for dag, full in ((False, brillouin_apply), (True, brillouin_apply_dagger)):
+        ref = full(brillouin_links(V), psi, 0.05, True, sites=sites)
+        got = brillouin_apply_sites(w81, psi, 0.05, sites, True, dagger=dag)
+        np.testing.assert_allclose(got, ref, atol=1e-14)
+    v32, p32 = V.astype(np.complex64), psi.astype(np.complex64)
+    a = brillouin_apply_sites(brillouin_links_all(v32, sites=sites), p32, 0.05, sites)
+    b = brillouin_apply_sites(brillouin_links_all(v32.astype(complex), sites=sites), p32.astype(complex), 0.05, sites)
+    assert a.dtype == np.complex128
+    np.testing.assert_array_equal(a, b)
