@@ -205,7 +205,11 @@ int bicgstab_solve(dirac_op op, dirac_prec outer, dirac_prec inner, const void* 
 /* Launch-shape knob for the stencil kernels of (op, prec): rb = right-hand sides handled by
  * one thread (0 automatic; 1, 2 or 4, Brillouin 1 or 2; used whenever it divides nv);
  * variant = 0 automatic, 1 direct global loads (hops unrolled), 2 LDS-staged site tiles,
- * 3 direct global loads with one hop direction per loop iteration (Wilson, staggered).
+ * 3 direct global loads with one hop direction per loop iteration (Wilson, staggered),
+ * 4 row tiles (Wilson: a work-group stages one x-row of the lattice in LDS with contiguous
+ * loads, the next hop direction in flight while the current one is consumed; rows taken in
+ * 4 x 4 (y, z) blocks with t next), 5 the same with the 1/2 applied per hop, 6 lexicographic
+ * rows, 7 t slabs (one per XCD) of 4 x 4 blocks.
  * Results agree to rounding whatever the shape.  Process-wide, not thread-safe. */
 int dirac_set_launch_shape(dirac_op op, dirac_prec prec, int rb, int variant);
 

@@ -91,17 +91,21 @@ int check_hip(hipError_t e, const char* what) {
     return DIRAC_EHIP;
 }
 
-// Default launch shapes, chosen by timing every shape at 16^3 x 32, Nc = 3, Nv = 12 on MI355X:
-//   Wilson   FP32: 2 RHS/thread, hops unrolled      FP64, BF16: 1 RHS/thread, one hop per iteration
+// Default launch shapes, chosen by timing every shape at 16^3 x 32 and 32^3 x 64, Nc = 3,
+// Nv = 12 on MI355X:
+//   Wilson: row tiles (one x-row per work-group staged in LDS), 1 RHS per thread; FP32 and FP64
+//           with the 1/2 applied per hop, BF16 with the hops summed unscaled (variant 4).  Shapes
+//           the row tiles cannot take fall back to direct loads with one hop per iteration.
 //   staggered: 2 RHS/thread, hops unrolled          Brillouin: 1 RHS/thread
 // A shape that does not divide nv falls back to fewer RHS per thread.
 int choose_rb(dirac_op op, dirac_prec prec, int nc, int nv) {
     const int o = g_rb_override[op][prec];
     if (o > 0 && nv % o == 0) return o;
     (void)nc;
+    (void)prec;
     switch (op) {
         case DIRAC_WILSON:
-            return (prec == DIRAC_FP32 && nv % 2 == 0) ? 2 : 1;
+            return 1;
         case DIRAC_STAGGERED:
             return nv % 2 == 0 ? 2 : 1;
         case DIRAC_BRILLOUIN:
@@ -110,11 +114,12 @@ int choose_rb(dirac_op op, dirac_prec prec, int nc, int nv) {
     return 1;
 }
 
-// 1 = direct loads with hops unrolled, 2 = LDS-staged tiles, 3 = direct loads, one hop per iteration
+// 1 = direct loads with hops unrolled, 2 = LDS-staged site tiles, 3 = direct loads, one hop per
+// iteration, 4..7 = row tiles (Wilson; see dirac_set_launch_shape)
 int choose_variant(dirac_op op, dirac_prec prec) {
     const int o = g_variant_override[op][prec];
     if (o > 0) return o;
-    if (op == DIRAC_WILSON && prec != DIRAC_FP32) return 3;
+    if (op == DIRAC_WILSON) return prec == DIRAC_BF16 ? 4 : 5;
     return 1;
 }
 
@@ -350,7 +355,7 @@ int dirac_set_launch_shape(dirac_op op, dirac_prec prec, int rb, int variant) {
     const int maxrb = op == DIRAC_BRILLOUIN ? 2 : 4;
     if (rb != 0 && rb != 1 && rb != 2 && rb != 4) return fail(DIRAC_EINVAL, "rb must be 0, 1, 2 or 4");
     if (rb > maxrb) return fail(DIRAC_EUNSUPPORTED, "rb not instantiated for this operator");
-    if (variant < 0 || variant > 3) return fail(DIRAC_EINVAL, "variant must be 0..3");
+    if (variant < 0 || variant > 7) return fail(DIRAC_EINVAL, "variant must be 0..7");
     g_rb_override[op][prec] = rb;
     g_variant_override[op][prec] = variant;
     return DIRAC_OK;

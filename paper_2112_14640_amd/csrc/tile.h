@@ -119,6 +119,103 @@ int choose_tile_sites(int nrg, F lds_of) {
     return S;
 }
 
+// ---------------------------------------------------------------------------
+// Row tiles.  Rows are the x-lines of the lattice, numbered rho = site / nx = y + ny (z + nz t).
+// A work-group owns one row (S = nx sites) and every right-hand side of it.  Its own row also
+// holds the +-x neighbours (periodic within the row); each of the other six hop directions needs
+// one whole row, a contiguous stretch of memory, so every copy into LDS is a contiguous
+// 16-byte-per-lane load.
+// ---------------------------------------------------------------------------
+struct RowTile {
+    int R;                 // rows per tile (1)
+    int S;                 // sites per tile, R * nx
+    int nrg;               // RHS groups per site (threads per site)
+    int units;             // 16-byte units per site block
+    int row_units;         // nx * units
+    int threads;           // S * nrg active threads
+    int64_t ntiles;        // rows / R
+    uint32_t magic_nrg, magic_nx, magic_units, magic_row_units;
+    // Tile order.  The t range is cut into slabs of ts slices, one slab per XCD when nt allows
+    // (the launch gives each XCD a contiguous eighth of the tiles), so only the +-t copies at a
+    // slab face come from another XCD's share.  Inside a slab: (y, z) blocks of by x bz rows,
+    // then t, then the rows of the block, so the rows a tile shares with its +-y, +-z and +-t
+    // neighbours are fetched close together in time.
+    int by, bz, nby, ts;
+};
+
+// First site of the row one step from row rho: dir 0..5 = +y, -y, +z, -z, +t, -t (periodic).
+__device__ __forceinline__ int64_t row_neighbour_start(uint32_t rho, int dir, const Geom& g) {
+    const uint32_t ny = static_cast<uint32_t>(g.ny), nz = static_cast<uint32_t>(g.nz);
+    const uint32_t q = rho / ny;
+    int y = static_cast<int>(rho - q * ny);
+    const uint32_t tq = q / nz;
+    int z = static_cast<int>(q - tq * nz);
+    int t = static_cast<int>(tq);
+    switch (dir) {
+        case 0: y = y + 1 == g.ny ? 0 : y + 1; break;
+        case 1: y = y == 0 ? g.ny - 1 : y - 1; break;
+        case 2: z = z + 1 == g.nz ? 0 : z + 1; break;
+        case 3: z = z == 0 ? g.nz - 1 : z - 1; break;
+        case 4: t = t + 1 == g.nt ? 0 : t + 1; break;
+        default: t = t == 0 ? g.nt - 1 : t - 1; break;
+    }
+    return ((static_cast<int64_t>(t) * g.nz + z) * g.ny + y) * g.nx;
+}
+
+// Bytes of LDS for one staged row tile (site stride padded by one 16-byte unit).
+inline size_t row_tile_lds(int S, int units) { return static_cast<size_t>(S) * (units + 1) * 16; }
+
+// Row processed by tile number T (after the XCD remap) in the order of RowTile.
+__device__ __forceinline__ uint32_t tile_row(uint32_t T, const RowTile& rt, const Geom& g) {
+    const uint32_t plane = static_cast<uint32_t>(g.ny * g.nz);
+    const uint32_t slab_rows = plane * static_cast<uint32_t>(rt.ts);
+    const uint32_t slab = T / slab_rows;
+    const uint32_t T2 = T - slab * slab_rows;
+    const uint32_t bsz = static_cast<uint32_t>(rt.by * rt.bz);
+    const uint32_t q = T2 / bsz;
+    const uint32_t rin = T2 - q * bsz;
+    const uint32_t b = q / static_cast<uint32_t>(rt.ts);
+    const uint32_t t = slab * rt.ts + (q - b * static_cast<uint32_t>(rt.ts));
+    const uint32_t bzi = b / static_cast<uint32_t>(rt.nby);
+    const uint32_t byi = b - bzi * static_cast<uint32_t>(rt.nby);
+    const uint32_t zin = rin / static_cast<uint32_t>(rt.by);
+    const uint32_t y = byi * rt.by + (rin - zin * rt.by);
+    const uint32_t z = bzi * rt.bz + zin;
+    return y + static_cast<uint32_t>(g.ny) * (z + static_cast<uint32_t>(g.nz) * t);
+}
+
+// Block extent of the row order along one axis: `want` when it divides n, else 2, else 1.
+inline int row_block_extent(int n, int want) { return n % want == 0 ? want : (n % 2 == 0 ? 2 : 1); }
+
+// Row order of variants 4 and 5 (4 x 4 (y, z) blocks over the whole t range), 6 (lexicographic),
+// 7 (t slabs, one per XCD, 4 x 4 blocks inside).
+inline void row_order(int variant, const Geom& g, RowTile& rt) {
+    if (variant == 6) {
+        rt.by = g.ny;
+        rt.bz = g.nz;
+        rt.ts = 1;
+    } else {
+        rt.by = row_block_extent(g.ny, 4);
+        rt.bz = row_block_extent(g.nz, 4);
+        rt.ts = g.nt;
+        if (variant == 7)
+            for (int parts : {8, 4, 2})
+                if (g.nt % parts == 0) {
+                    rt.ts = g.nt / parts;
+                    break;
+                }
+    }
+    rt.nby = g.ny / rt.by;
+}
+
+// Row tiles are used for variants 4..7 when one row of every RHS fits: at most 512 threads
+// and 64 KiB of LDS.  Returns the rows per tile (1) or 0.
+inline int choose_tile_rows(int, int64_t rows, int nx, int units, int nrg) {
+    const int64_t threads = static_cast<int64_t>(nx) * nrg;
+    if (rows >= 1 && threads >= 64 && threads <= 512 && row_tile_lds(nx, units) <= 64 * 1024) return 1;
+    return 0;
+}
+
 // The LDS-staged tiles are used when variant 2 is selected (see choose_variant).
 inline bool use_lds_variant(const StencilArgs& a, bool = true) { return a.variant == 2; }
 

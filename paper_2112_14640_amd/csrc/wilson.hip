@@ -97,12 +97,10 @@ __device__ __forceinline__ void reconstruct_add(cx<R> acc[4], cx<R> c0, cx<R> c1
     }
 }
 
-// acc += scale * (1 + SIG g_MU) L u_nb, with L = link (ADJ = false) or link^+ (ADJ = true).
-template <int NC, int RB, int MU, int SIG, bool ADJ, class P>
-__device__ __forceinline__ void hop(cx<typename P::R> (&acc)[RB][NC][4], const typename P::G* __restrict__ link,
-                                    const typename P::S* __restrict__ nb, int nv, typename P::R scale) {
+// L = link (ADJ = false) or link^+ (ADJ = true) into registers.
+template <int NC, bool ADJ, class P>
+__device__ __forceinline__ void load_link(cx<typename P::R> (&l)[NC][NC], const typename P::G* __restrict__ link) {
     using R = typename P::R;
-    cx<R> l[NC][NC];
 #pragma unroll
     for (int a = 0; a < NC; ++a)
 #pragma unroll
@@ -114,6 +112,15 @@ __device__ __forceinline__ void hop(cx<typename P::R> (&acc)[RB][NC][4], const t
                 l[a][b] = v;
             }
         }
+}
+
+// acc += scale * (1 + SIG g_MU) L u_nb for a link matrix L already in registers.  SCALED = false
+// skips the scale (taken as 1); NVC > 0 fixes the RHS stride at compile time (else nv).
+template <int NC, int RB, int MU, int SIG, class P, bool SCALED = true, int NVC = 0>
+__device__ __forceinline__ void hop_with(cx<typename P::R> (&acc)[RB][NC][4], const cx<typename P::R> (&l)[NC][NC],
+                                         const typename P::S* __restrict__ nb, int nv, typename P::R scale) {
+    using R = typename P::R;
+    const int stride = NVC > 0 ? NVC : nv;
 #pragma unroll
     for (int k = 0; k < RB; ++k) {
         cx<R> h0[NC], h1[NC];
@@ -121,10 +128,12 @@ __device__ __forceinline__ void hop(cx<typename P::R> (&acc)[RB][NC][4], const t
         for (int b = 0; b < NC; ++b) {
             cx<R> p[4];
 #pragma unroll
-            for (int s = 0; s < 4; ++s) p[s] = io<R, typename P::S>::ld(nb + (b * 4 + s) * nv + k);
+            for (int s = 0; s < 4; ++s) p[s] = io<R, typename P::S>::ld(nb + (b * 4 + s) * stride + k);
             project<MU, SIG>(p, h0[b], h1[b]);
-            h0[b] = cscale(scale, h0[b]);
-            h1[b] = cscale(scale, h1[b]);
+            if constexpr (SCALED) {
+                h0[b] = cscale(scale, h0[b]);
+                h1[b] = cscale(scale, h1[b]);
+            }
         }
 #pragma unroll
         for (int a = 0; a < NC; ++a) {
@@ -137,6 +146,15 @@ __device__ __forceinline__ void hop(cx<typename P::R> (&acc)[RB][NC][4], const t
             reconstruct_add<MU, SIG>(acc[k][a], c0, c1);
         }
     }
+}
+
+// acc += scale * (1 + SIG g_MU) L u_nb, with L = link (ADJ = false) or link^+ (ADJ = true).
+template <int NC, int RB, int MU, int SIG, bool ADJ, class P>
+__device__ __forceinline__ void hop(cx<typename P::R> (&acc)[RB][NC][4], const typename P::G* __restrict__ link,
+                                    const typename P::S* __restrict__ nb, int nv, typename P::R scale) {
+    cx<typename P::R> l[NC][NC];
+    load_link<NC, ADJ, P>(l, link);
+    hop_with<NC, RB, MU, SIG, P>(acc, l, nb, nv, scale);
 }
 
 // Direction-generic hop (runtime mu and projector sign, wave-uniform).  With P = 1 + sig g_mu
@@ -404,6 +422,209 @@ __global__ __launch_bounds__(512) void wilson_lds_kernel(const typename P::G* __
     tile_scatter_out(reinterpret_cast<Unit*>(out) + s0 * tg.units, tile, nsites, tg);
 }
 
+
+// Row-tiled variant (see RowTile).  Seven row copies per tile: the own rows (mass term and the
+// +-x hops) and the rows one step away in +y, -y, +z, -z, +t, -t.  The copy of the next
+// direction is issued into registers before the current direction is consumed from LDS, so the
+// loads of one direction overlap the arithmetic of the previous one.  The output tile leaves
+// through LDS as one contiguous store.
+template <int NC, int RB, class P>
+struct RowUnits {
+    // 16-byte units each thread moves per row copy: its share of the tile
+    static constexpr int PER = NC * 4 * RB * static_cast<int>(sizeof(typename P::S)) / 16;
+};
+
+using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
+
+template <int NC, int RB, bool DAG, class P, int NVC, bool UNSCALED>
+__global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* __restrict__ U,
+                                                          const typename P::S* __restrict__ in,
+                                                          typename P::S* __restrict__ out, typename P::R diag,
+                                                          Geom g, int nv, RowTile rt) {
+    using R = typename P::R;
+    using S = typename P::S;
+    constexpr int PER = RowUnits<NC, RB, P>::PER;
+    constexpr int L = NC * NC;
+    extern __shared__ __align__(16) u32x4 rtile[];
+
+    const int64_t tix = logical_block();
+    if (tix >= rt.ntiles) return;
+    const uint32_t rho = tile_row(static_cast<uint32_t>(tix), rt, g);  // one row per work-group
+    const uint32_t tid = threadIdx.x;
+    const bool active = tid < static_cast<uint32_t>(rt.threads);
+    // padding threads (block rounded up to whole wavefronts) shadow a real thread: same loads and
+    // LDS writes of the same values, no global store
+    const uint32_t tt = active ? tid : tid - rt.threads;
+    const uint32_t j = fast_div(tt, rt.magic_nrg);  // x of this thread's site
+    const int rg = static_cast<int>(tt - j * rt.nrg);
+    const int x = static_cast<int>(j);
+    const int64_t rowsite = static_cast<int64_t>(rho) * g.nx;
+    const int64_t site = rowsite + x;
+    const int ct = static_cast<int>(rho / static_cast<uint32_t>(g.ny) / static_cast<uint32_t>(g.nz));
+    const u32x4* src = reinterpret_cast<const u32x4*>(in);
+    if constexpr (NVC > 0) nv = NVC;
+
+    // unit k of this thread: k * threads + tt of the row copy; its padded LDS slot
+    uint32_t slot[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const uint32_t u = k * static_cast<uint32_t>(rt.threads) + tt;
+        slot[k] = u + fast_div(u, rt.magic_units);
+    }
+    u32x4 pre[PER];
+    auto fetch = [&](int64_t row_start) __attribute__((always_inline)) {
+        const u32x4* p = src + row_start * rt.units + tt;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) pre[k] = p[static_cast<int64_t>(k) * rt.threads];
+    };
+    auto stash = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) rtile[slot[k]] = pre[k];
+    };
+    auto at = [&](uint32_t jj) __attribute__((always_inline)) {
+        return reinterpret_cast<const S*>(rtile + jj * (rt.units + 1)) + rg * RB;
+    };
+
+    cx<R> acc[RB][NC][4];
+    constexpr int SF = DAG ? 1 : -1;  // forward projector 1 + SF g_mu
+    // Links are loaded one direction ahead and before the next row copy: loads complete in issue
+    // order, so waiting for a link never waits for the row copy still in flight.
+    const int xp = x + 1 == g.nx ? 0 : x + 1;
+    const int xm = x == 0 ? g.nx - 1 : x - 1;
+    cx<R> lxp[NC][NC], lxm[NC][NC], lnext[NC][NC];
+    fetch(rowsite);
+    load_link<NC, false, P>(lxp, U + (site * 4 + 0) * L);
+    load_link<NC, true, P>(lxm, U + ((rowsite + xm) * 4 + 0) * L);
+    stash();
+    __syncthreads();
+    fetch(row_neighbour_start(rho, 0, g));
+    load_link<NC, false, P>(lnext, U + (site * 4 + 1) * L);
+    // UNSCALED: the hops are summed without the 1/2 (acc starts at -2 (4 + m) u and is multiplied
+    // by -1/2 at the end); otherwise each half spinor is scaled by -1/2 (or +1/2 across the t
+    // boundary) before the link multiply
+    const R c0 = UNSCALED ? R(-2) * diag : diag;
+    if (active) {
+        const S* mine = at(j);
+#pragma unroll
+        for (int k = 0; k < RB; ++k)
+#pragma unroll
+            for (int a = 0; a < NC; ++a)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) acc[k][a][s] = cscale(c0, io<R, S>::ld(mine + (a * 4 + s) * nv + k));
+        hop_with<NC, RB, 0, SF, P, !UNSCALED, NVC>(acc, lxp, at(xp), nv, R(-0.5));
+        hop_with<NC, RB, 0, -SF, P, !UNSCALED, NVC>(acc, lxm, at(xm), nv, R(-0.5));
+    }
+    auto step = [&](auto mu_c, auto back_c) __attribute__((always_inline)) {
+        constexpr int MU = decltype(mu_c)::value;
+        constexpr bool BACK = decltype(back_c)::value;
+        constexpr int DIR = 2 * (MU - 1) + (BACK ? 1 : 0);
+        cx<R> lcur[NC][NC];
+#pragma unroll
+        for (int a = 0; a < NC; ++a)
+#pragma unroll
+            for (int b = 0; b < NC; ++b) lcur[a][b] = lnext[a][b];
+        __syncthreads();
+        stash();
+        __syncthreads();
+        if constexpr (DIR < 5) {
+            constexpr int ND = DIR + 1;
+            constexpr int NMU = ND / 2 + 1;
+            const int64_t nrow = row_neighbour_start(rho, ND, g);
+            fetch(nrow);
+            if constexpr (ND % 2 == 0) {
+                load_link<NC, false, P>(lnext, U + (site * 4 + NMU) * L);
+            } else {
+                load_link<NC, true, P>(lnext, U + ((nrow + x) * 4 + NMU) * L);
+            }
+        }
+        if (active) {
+            const bool wrap = MU == 3 && g.apbc && ct == (BACK ? 0 : g.nt - 1);  // fermion sign
+            if constexpr (UNSCALED) {
+                if (wrap) {
+#pragma unroll
+                    for (int a = 0; a < NC; ++a)
+#pragma unroll
+                        for (int b = 0; b < NC; ++b) lcur[a][b] = cscale(R(-1), lcur[a][b]);
+                }
+            }
+            hop_with<NC, RB, MU, (BACK ? -SF : SF), P, !UNSCALED, NVC>(acc, lcur, at(j), nv,
+                                                                        wrap ? R(0.5) : R(-0.5));
+        }
+    };
+    step(std::integral_constant<int, 1>{}, std::false_type{});
+    step(std::integral_constant<int, 1>{}, std::true_type{});
+    step(std::integral_constant<int, 2>{}, std::false_type{});
+    step(std::integral_constant<int, 2>{}, std::true_type{});
+    step(std::integral_constant<int, 3>{}, std::false_type{});
+    step(std::integral_constant<int, 3>{}, std::true_type{});
+    __syncthreads();
+    if (active) {
+        S* o = const_cast<S*>(at(j));
+#pragma unroll
+        for (int k = 0; k < RB; ++k)
+#pragma unroll
+            for (int a = 0; a < NC; ++a)
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    io<R, S>::st(o + (a * 4 + s) * nv + k, UNSCALED ? cscale(R(-0.5), acc[k][a][s]) : acc[k][a][s]);
+    }
+    __syncthreads();
+    u32x4* dst = reinterpret_cast<u32x4*>(out) + rowsite * rt.units;
+    const uint32_t total = static_cast<uint32_t>(rt.S) * rt.units;
+    for (uint32_t u = tid; u < total; u += blockDim.x) dst[u] = rtile[u + fast_div(u, rt.magic_units)];
+}
+
+template <int NC, int RB, class P>
+bool launch_rows(const StencilArgs& a, hipStream_t st) {
+    using S = typename P::S;
+    const size_t block_bytes = static_cast<size_t>(NC) * 4 * a.nv * sizeof(S);
+    if (block_bytes % 16 != 0 || !tile_aligned(a)) return false;
+    const int units = static_cast<int>(block_bytes / 16);
+    const int nrg = a.nv / RB;
+    const int64_t rows = a.g.vol / a.g.nx;
+    const int Rr = choose_tile_rows(a.variant, rows, a.g.nx, units, nrg);
+    if (Rr == 0) return false;
+    RowTile rt;
+    rt.R = Rr;
+    rt.S = Rr * a.g.nx;
+    rt.nrg = nrg;
+    rt.units = units;
+    rt.row_units = a.g.nx * units;
+    rt.threads = rt.S * nrg;
+    rt.ntiles = rows / Rr;
+    rt.magic_nrg = div_magic(nrg);
+    rt.magic_nx = div_magic(a.g.nx);
+    rt.magic_units = div_magic(units);
+    rt.magic_row_units = div_magic(rt.row_units);
+    row_order(a.variant, a.g, rt);
+    const int block = (rt.threads + 63) / 64 * 64;
+    const size_t lds = row_tile_lds(rt.S, units);
+    const dim3 grid(static_cast<unsigned>(grid_blocks_x8(rt.ntiles, 1)));
+    using R = typename P::R;
+    const R diag = static_cast<R>(4.0 + a.mass);
+    auto U = static_cast<const typename P::G*>(a.gauge);
+    auto in = static_cast<const S*>(a.in);
+    auto out = static_cast<S*>(a.out);
+    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, grid, dim3(block), lds, st, U, in, out, diag, a.g, a.nv, rt); };
+    if (a.variant == 5) {  // per-hop scaling, runtime RHS stride
+        if (a.dagger)
+            go(wilson_rows_kernel<NC, RB, true, P, 0, false>);
+        else
+            go(wilson_rows_kernel<NC, RB, false, P, 0, false>);
+    } else if (a.nv == 12 && RB == 1) {  // the common multi-RHS count: component offsets become constants
+        if (a.dagger)
+            go(wilson_rows_kernel<NC, RB, true, P, 12, true>);
+        else
+            go(wilson_rows_kernel<NC, RB, false, P, 12, true>);
+    } else {
+        if (a.dagger)
+            go(wilson_rows_kernel<NC, RB, true, P, 0, true>);
+        else
+            go(wilson_rows_kernel<NC, RB, false, P, 0, true>);
+    }
+    return true;
+}
+
 template <int NC, int RB, class P>
 bool launch_lds(const StencilArgs& a, hipStream_t st) {
     using R = typename P::R;
@@ -437,6 +658,13 @@ bool launch_lds(const StencilArgs& a, hipStream_t st) {
 template <int NC, int RB, class P>
 void launch_rb(const StencilArgs& a, hipStream_t st) {
     using R = typename P::R;
+    if (a.variant >= 4 && a.variant <= 7) {
+        if (launch_rows<NC, RB, P>(a, st)) return;
+        StencilArgs b = a;  // the row tile does not fit: direct loads, one hop per iteration
+        b.variant = 3;
+        launch_rb<NC, RB, P>(b, st);
+        return;
+    }
     if (use_lds_variant(a) && launch_lds<NC, RB, P>(a, st)) return;
     const int block = 256;
     const int64_t threads = a.g.vol * (a.nv / RB);

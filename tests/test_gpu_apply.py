@@ -184,7 +184,7 @@ def test_free_field_plane_wave_16x32():
     assert col_rel_err(host(v), expect) < 1e-12
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("rb", [1, 2, 4])
 @pytest.mark.parametrize("op", ["wilson", "staggered", "brillouin"])
 def test_launch_shapes_agree(op, rb, variant):
@@ -200,6 +200,36 @@ def test_launch_shapes_agree(op, rb, variant):
         dirac.set_launch_shape(op, "fp32", 0, 0)
     ref = ORACLE[(op, False)](g_in, u_in, 0.1, True)
     assert col_rel_err(v, ref) < 1e-5
+
+
+ROW_CASES = [
+    # dims, nc, nv, antiperiodic: rows of 6, 4, 3 and 10 sites, one to four rows per tile
+    ((6, 4, 4, 6), 3, 12, True),
+    ((4, 2, 6, 4), 2, 4, False),
+    ((3, 2, 2, 4), 3, 6, True),
+    ((10, 2, 2, 2), 1, 2, True),
+    ((4, 4, 2, 6), 4, 1, True),
+]
+
+
+@pytest.mark.parametrize("variant", [4, 5, 6, 7])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("case", range(len(ROW_CASES)))
+def test_wilson_row_tiles(case, prec, variant):
+    """The row-tiled Wilson kernel (every rows-per-tile choice, 1 and 2 RHS per thread) against the oracle."""
+    dims, nc, nv, apbc = ROW_CASES[case]
+    gauge, u = _inputs("wilson", dims, nc, nv, seed=40 + case)
+    for rb in (1, 2):
+        if nv % rb:
+            continue
+        try:
+            dirac.set_launch_shape("wilson", prec, rb, variant)
+            for dagger in (False, True):
+                v, g_in, u_in = _run("wilson", prec, gauge, u, 0.03, apbc, dagger)
+                err = col_rel_err(v, ORACLE[("wilson", dagger)](g_in, u_in, 0.03, apbc))
+                assert err < TOL[prec], (dims, nc, nv, rb, dagger, err)
+        finally:
+            dirac.set_launch_shape("wilson", prec, 0, 0)
 
 
 def test_invalid_arguments_raise():
