@@ -186,7 +186,7 @@ typedef struct {
     int recompute_every;  /* 0: default (50 FP64, 20 lower) */
     double drift;         /* 0: default 0.01 */
     int mixed_scheme;     /* 0: reliable updates (default), 1: defect correction (restarted inner solves) */
-    double delta;         /* reliable update / inner reduction factor; 0: default (0.1 FP32, 0.5 BF16) */
+    double delta;         /* reliable update / inner reduction factor; 0: default (0.1) */
     int max_outer;        /* defect-correction cycles; 0: default 100 */
 } dirac_solve_opts;
 
@@ -209,7 +209,10 @@ int bicgstab_solve(dirac_op op, dirac_prec outer, dirac_prec inner, const void* 
  * 4 row tiles (Wilson: a work-group stages one x-row of the lattice in LDS with contiguous
  * loads, the next hop direction in flight while the current one is consumed; rows taken in
  * 4 x 4 (y, z) blocks with t next), 5 the same with the 1/2 applied per hop, 6 lexicographic
- * rows, 7 t slabs (one per XCD) of 4 x 4 blocks.
+ * rows, 7 t slabs (one per XCD) of 4 x 4 blocks.  Brillouin: 4 row tiles (a work-group walks
+ * the 27 neighbouring x-rows of its row, each staged in LDS with a window of three links per
+ * site), anything else direct global loads.  Staggered: 4 row tiles as for Wilson (one x-row
+ * per work-group, the six other neighbour rows staged in turn).
  * Results agree to rounding whatever the shape.  Process-wide, not thread-safe. */
 int dirac_set_launch_shape(dirac_op op, dirac_prec prec, int rb, int variant);
 

@@ -96,7 +96,9 @@ int check_hip(hipError_t e, const char* what) {
 //   Wilson: row tiles (one x-row per work-group staged in LDS), 1 RHS per thread; FP32 and FP64
 //           with the 1/2 applied per hop, BF16 with the hops summed unscaled (variant 4).  Shapes
 //           the row tiles cannot take fall back to direct loads with one hop per iteration.
-//   staggered: 2 RHS/thread, hops unrolled          Brillouin: 1 RHS/thread
+//   staggered: row tiles, 2 RHS/thread (direct loads with the hops unrolled where a row does not fit)
+//   Brillouin: 1 RHS/thread; FP32 and BF16 row tiles (27 row copies per x-row, link windows in
+//              LDS), FP64 direct loads (the row tile spills registers in FP64)
 // A shape that does not divide nv falls back to fewer RHS per thread.
 int choose_rb(dirac_op op, dirac_prec prec, int nc, int nv) {
     const int o = g_rb_override[op][prec];
@@ -107,7 +109,7 @@ int choose_rb(dirac_op op, dirac_prec prec, int nc, int nv) {
         case DIRAC_WILSON:
             return 1;
         case DIRAC_STAGGERED:
-            return nv % 2 == 0 ? 2 : 1;
+            return nv % 2 == 0 ? 2 : 1;  // row tiles with 2 RHS per thread
         case DIRAC_BRILLOUIN:
             return 1;
     }
@@ -120,7 +122,8 @@ int choose_variant(dirac_op op, dirac_prec prec) {
     const int o = g_variant_override[op][prec];
     if (o > 0) return o;
     if (op == DIRAC_WILSON) return prec == DIRAC_BF16 ? 4 : 5;
-    return 1;
+    if (op == DIRAC_BRILLOUIN) return prec == DIRAC_FP64 ? 1 : 4;
+    return 4;  // staggered
 }
 
 size_t solver_workspace_bytes(dirac_op op, int solver, dirac_prec outer, dirac_prec inner, int nc, int nv,

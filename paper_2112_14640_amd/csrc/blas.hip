@@ -106,6 +106,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_norm2(const SX* __restrict__
     double acc[1] = {0.0};
     if (rl.roff < rl.rpb) {
         const int64_t step = static_cast<int64_t>(gridDim.x) * rl.rpb;
+#pragma unroll 4
         for (int64_t row = static_cast<int64_t>(blockIdx.x) * rl.rpb + rl.roff; row < nrows; row += step) {
             cx<double> v = ldd(x + row * nv + rl.rhs);
             acc[0] += v.re * v.re + v.im * v.im;
@@ -121,6 +122,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_dot(const SX* __restrict__ x
     double acc[2] = {0.0, 0.0};
     if (rl.roff < rl.rpb) {
         const int64_t step = static_cast<int64_t>(gridDim.x) * rl.rpb;
+#pragma unroll 4
         for (int64_t row = static_cast<int64_t>(blockIdx.x) * rl.rpb + rl.roff; row < nrows; row += step) {
             cx<double> a = ldd(x + row * nv + rl.rhs);
             cx<double> b = ldd(y + row * nv + rl.rhs);
@@ -234,6 +236,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_r_update(SR* __restrict__ r,
         const double2 al = alpha[rl.rhs];
         const cx<double> ma{-al.x, -al.y};
         const int64_t step = static_cast<int64_t>(gridDim.x) * rl.rpb;
+#pragma unroll 4
         for (int64_t row = static_cast<int64_t>(blockIdx.x) * rl.rpb + rl.roff; row < nrows; row += step) {
             const int64_t i = row * nv + rl.rhs;
             cx<double> rv = ldd(r + i);
@@ -278,6 +281,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_bicg_xr(S* __restrict__ x, c
         const double2 al = alpha[rl.rhs], om = omega[rl.rhs];
         const cx<double> a{al.x, al.y}, w{om.x, om.y}, mw{-om.x, -om.y};
         const int64_t step = static_cast<int64_t>(gridDim.x) * rl.rpb;
+#pragma unroll 4
         for (int64_t row = static_cast<int64_t>(blockIdx.x) * rl.rpb + rl.roff; row < nrows; row += step) {
             const int64_t i = row * nv + rl.rhs;
             const cx<double> sv = ldd(s + i);

@@ -12,8 +12,11 @@
 // which is Eq. app_bril with the derivative factor of Eq. def_ider written out; the adjoint
 // negates the rho part (g_5-hermiticity).  In the chiral basis sum_mu c_mu g_mu is
 // [[0, B], [B^+, 0]] with B = [[c4 - i c3, -c2 - i c1], [c2 - i c1, c4 + i c3]] (App. C).
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
+#include "tile.h"
 
 namespace dirac {
 
@@ -109,6 +112,47 @@ __global__ __launch_bounds__(256) void links_kernel(const GI* __restrict__ U, GO
 // Apply: one thread per (site, RB right-hand sides); the 80 directions are a runtime loop
 // with wave-uniform direction data.
 // ---------------------------------------------------------------------------
+// o[s] += (sum_mu q_mu g_mu - lh) ch[s] in the chiral basis, one displacement component at a time
+// (hx..ht: d_x..d_t non-zero; q_mu = rho_k d_mu, already carrying the adjoint's and the boundary's
+// signs, as does lh):
+//   g_4: rows (0,1,2,3) <- (2,3,0,1)
+//   g_3: rows <- (-i 2, +i 3, +i 0, -i 1)
+//   g_2: rows <- (-3, +2, +1, -0)
+//   g_1: rows <- (-i 3, -i 2, +i 1, +i 0)
+template <typename R>
+__device__ __forceinline__ void spin_accumulate(cx<R> (&o)[4], const cx<R> (&ch)[4], R lh, R q1, R q2, R q3, R q4,
+                                                bool hx, bool hy, bool hz, bool ht) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        o[s].re -= lh * ch[s].re;
+        o[s].im -= lh * ch[s].im;
+    }
+    if (ht) {
+        o[0].re += q4 * ch[2].re; o[0].im += q4 * ch[2].im;
+        o[1].re += q4 * ch[3].re; o[1].im += q4 * ch[3].im;
+        o[2].re += q4 * ch[0].re; o[2].im += q4 * ch[0].im;
+        o[3].re += q4 * ch[1].re; o[3].im += q4 * ch[1].im;
+    }
+    if (hz) {
+        o[0].re += q3 * ch[2].im; o[0].im -= q3 * ch[2].re;
+        o[1].re -= q3 * ch[3].im; o[1].im += q3 * ch[3].re;
+        o[2].re -= q3 * ch[0].im; o[2].im += q3 * ch[0].re;
+        o[3].re += q3 * ch[1].im; o[3].im -= q3 * ch[1].re;
+    }
+    if (hy) {
+        o[0].re -= q2 * ch[3].re; o[0].im -= q2 * ch[3].im;
+        o[1].re += q2 * ch[2].re; o[1].im += q2 * ch[2].im;
+        o[2].re += q2 * ch[1].re; o[2].im += q2 * ch[1].im;
+        o[3].re -= q2 * ch[0].re; o[3].im -= q2 * ch[0].im;
+    }
+    if (hx) {
+        o[0].re += q1 * ch[3].im; o[0].im -= q1 * ch[3].re;
+        o[1].re += q1 * ch[2].im; o[1].im -= q1 * ch[2].re;
+        o[2].re -= q1 * ch[1].im; o[2].im += q1 * ch[1].re;
+        o[3].re -= q1 * ch[0].im; o[3].im += q1 * ch[0].re;
+    }
+}
+
 template <int NC, int RB, bool DAG, class P>
 __global__ __launch_bounds__(256) void brillouin_kernel(const typename P::G* __restrict__ W,
                                                          const typename P::S* __restrict__ in,
@@ -149,11 +193,12 @@ __global__ __launch_bounds__(256) void brillouin_kernel(const typename P::G* __r
         // wave-uniform direction data
         const int ix = dir % 3, iy = (dir / 3) % 3, iz = (dir / 9) % 3, it = dir / 27;
         const int kh = (ix != 1) + (iy != 1) + (iz != 1) + (it != 1);
-        const R rho = static_cast<R>(DAG ? -c_rho[kh] : c_rho[kh]);
-        const R q1 = rho * (ix - 1), q2 = rho * (iy - 1), q3 = rho * (iz - 1), q4 = rho * (it - 1);
-        const R lh = static_cast<R>(c_halflam[kh]);
-        const int64_t nb = site + (ox[ix] + oy[iy] + oz[iz] + ot[it]);
+        // the fermion sign of a t-wrapping hop rides on the spin factor (five scalars)
         const R bsign = sgn_t[it];
+        const R rho = bsign * static_cast<R>(DAG ? -c_rho[kh] : c_rho[kh]);
+        const R q1 = rho * (ix - 1), q2 = rho * (iy - 1), q3 = rho * (iz - 1), q4 = rho * (it - 1);
+        const R lh = bsign * static_cast<R>(c_halflam[kh]);
+        const int64_t nb = site + (ox[ix] + oy[iy] + oz[iz] + ot[it]);
 
         cx<R> l[NC][NC];
         if (dir < 40) {
@@ -161,13 +206,13 @@ __global__ __launch_bounds__(256) void brillouin_kernel(const typename P::G* __r
 #pragma unroll
             for (int a = 0; a < NC; ++a)
 #pragma unroll
-                for (int b = 0; b < NC; ++b) l[a][b] = cscale(bsign, io<R, typename P::G>::ld(lp + a * NC + b));
+                for (int b = 0; b < NC; ++b) l[a][b] = io<R, typename P::G>::ld(lp + a * NC + b);
         } else {
             const typename P::G* lp = W + (nb * 40 + (80 - dir)) * NC * NC;
 #pragma unroll
             for (int a = 0; a < NC; ++a)
 #pragma unroll
-                for (int b = 0; b < NC; ++b) l[b][a] = cscale(bsign, cconj(io<R, typename P::G>::ld(lp + a * NC + b)));
+                for (int b = 0; b < NC; ++b) l[b][a] = cconj(io<R, typename P::G>::ld(lp + a * NC + b));
         }
         const S* nbp = in + nb * vs + r0;
 #pragma unroll
@@ -184,42 +229,7 @@ __global__ __launch_bounds__(256) void brillouin_kernel(const typename P::G* __r
                 for (int b = 0; b < NC; ++b)
 #pragma unroll
                     for (int s = 0; s < 4; ++s) cfma(ch[s], l[a][b], p[b][s]);
-                cx<R>* o = acc[k][a];
-                // -lambda_k/2 (spin diagonal)
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    o[s].re -= lh * ch[s].re;
-                    o[s].im -= lh * ch[s].im;
-                }
-                // rho_k sum_mu d_mu g_mu in the chiral basis, one displacement component at a time:
-                //   g_4: rows (0,1,2,3) <- (2,3,0,1)
-                //   g_3: rows <- (-i 2, +i 3, +i 0, -i 1)
-                //   g_2: rows <- (-3, +2, +1, -0)
-                //   g_1: rows <- (-i 3, -i 2, +i 1, +i 0)
-                if (it != 1) {
-                    o[0].re += q4 * ch[2].re; o[0].im += q4 * ch[2].im;
-                    o[1].re += q4 * ch[3].re; o[1].im += q4 * ch[3].im;
-                    o[2].re += q4 * ch[0].re; o[2].im += q4 * ch[0].im;
-                    o[3].re += q4 * ch[1].re; o[3].im += q4 * ch[1].im;
-                }
-                if (iz != 1) {
-                    o[0].re += q3 * ch[2].im; o[0].im -= q3 * ch[2].re;
-                    o[1].re -= q3 * ch[3].im; o[1].im += q3 * ch[3].re;
-                    o[2].re -= q3 * ch[0].im; o[2].im += q3 * ch[0].re;
-                    o[3].re += q3 * ch[1].im; o[3].im -= q3 * ch[1].re;
-                }
-                if (iy != 1) {
-                    o[0].re -= q2 * ch[3].re; o[0].im -= q2 * ch[3].im;
-                    o[1].re += q2 * ch[2].re; o[1].im += q2 * ch[2].im;
-                    o[2].re += q2 * ch[1].re; o[2].im += q2 * ch[1].im;
-                    o[3].re -= q2 * ch[0].re; o[3].im -= q2 * ch[0].im;
-                }
-                if (ix != 1) {
-                    o[0].re += q1 * ch[3].im; o[0].im -= q1 * ch[3].re;
-                    o[1].re += q1 * ch[2].im; o[1].im -= q1 * ch[2].re;
-                    o[2].re -= q1 * ch[1].im; o[2].im += q1 * ch[1].re;
-                    o[3].re -= q1 * ch[0].im; o[3].im += q1 * ch[0].re;
-                }
+                spin_accumulate(acc[k][a], ch, lh, q1, q2, q3, q4, ix != 1, iy != 1, iz != 1, it != 1);
             }
         }
     }
@@ -233,9 +243,237 @@ __global__ __launch_bounds__(256) void brillouin_kernel(const typename P::G* __r
             for (int s = 0; s < 4; ++s) io<R, S>::st(o + (a * 4 + s) * nv + k, acc[k][a][s]);
 }
 
+
+// Row-tiled apply: a work-group owns one x-row (every RHS) and walks the 27 rows at (y, z, t)
+// offsets in {-1,0,1}^3 (row copy rc = 9 (d_t+1) + 3 (d_z+1) + (d_y+1)).  Each such row is copied
+// into LDS with contiguous 16-byte loads and serves the three directions d_x = -1, 0, +1
+// (periodic within the row).  With it comes a window of three consecutive stored links per
+// site of one row: for rc < 13 the directions dir0 .. dir0 + 2 (dir0 = 27 it + 9 iz + 3 iy) of the
+// own row; for rc > 13 the directions 78 - dir0 .. 80 - dir0 of the neighbour row, whose adjoints
+// are the links of the directions 80 - dir (Tab. off-axis); for rc = 13 direction 39 of the own
+// row serves d_x = -1 as stored and d_x = +1 as the adjoint at x + 1.  The next row copy is in
+// flight (in registers) while the current one is consumed.
+template <int NC, int RB, bool DAG, class P, int NVC>
+__global__ __launch_bounds__(512) void brillouin_rows_kernel(const typename P::G* __restrict__ W,
+                                                             const typename P::S* __restrict__ in,
+                                                             typename P::S* __restrict__ out, typename P::R diag,
+                                                             Geom g, int nv, RowTile rt) {
+    using R = typename P::R;
+    using S = typename P::S;
+    using G = typename P::G;
+    constexpr int PER = RowUnits<NC, RB, P>::PER;
+    constexpr int L = NC * NC;
+    constexpr int LW = 3 * L;  // link-window elements per site
+    extern __shared__ __align__(16) u32x4 rtile[];
+    if constexpr (NVC > 0) nv = NVC;
+
+    const int64_t tix = logical_block();
+    if (tix >= rt.ntiles) return;
+    const uint32_t rho = tile_row(static_cast<uint32_t>(tix), rt, g);
+    const uint32_t tid = threadIdx.x;
+    const bool active = tid < static_cast<uint32_t>(rt.threads);
+    const uint32_t tt = active ? tid : tid - rt.threads;  // padding threads shadow a real one
+    const uint32_t j = fast_div(tt, rt.magic_nrg);
+    const int rg = static_cast<int>(tt - j * rt.nrg);
+    const int x = static_cast<int>(j);
+    int cy, cz, ct;
+    {
+        const uint32_t q = rho / static_cast<uint32_t>(g.ny);
+        cy = static_cast<int>(rho - q * g.ny);
+        const uint32_t q2 = q / static_cast<uint32_t>(g.nz);
+        cz = static_cast<int>(q - q2 * g.nz);
+        ct = static_cast<int>(q2);
+    }
+    const int64_t own_start = static_cast<int64_t>(rho) * g.nx;
+    const u32x4* src = reinterpret_cast<const u32x4*>(in);
+    G* lwin = reinterpret_cast<G*>(rtile + rt.S * (rt.units + 1));  // S * LW link elements
+    const uint32_t nlink = static_cast<uint32_t>(rt.S) * LW;
+    constexpr int PERL = 4;  // link elements per thread (threads >= 64 * ... checked at launch)
+    uint32_t slot[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const uint32_t u = k * static_cast<uint32_t>(rt.threads) + tt;
+        slot[k] = u + fast_div(u, rt.magic_units);
+    }
+    auto row_start = [&](int rc) __attribute__((always_inline)) {
+        const int dy = rc % 3 - 1, dz = (rc / 3) % 3 - 1, dt = rc / 9 - 1;
+        const int y = wrap(cy + dy, g.ny), z = wrap(cz + dz, g.nz), t = wrap(ct + dt, g.nt);
+        return ((static_cast<int64_t>(t) * g.nz + z) * g.ny + y) * g.nx;
+    };
+    u32x4 pre[PER];
+    G lpre[PERL];
+    auto fetch = [&](int rc) __attribute__((always_inline)) {
+        const int64_t start = row_start(rc);
+        const u32x4* p = src + start * rt.units + tt;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) pre[k] = p[static_cast<int64_t>(k) * rt.threads];
+        const int dir0 = 9 * (3 * (rc / 9) + (rc / 3) % 3) + 3 * (rc % 3);
+        const int64_t lstart = rc < 13 ? own_start : (rc == 13 ? own_start : start);
+        const int wb = rc < 13 ? dir0 : (rc == 13 ? 37 : 78 - dir0);
+#pragma unroll
+        for (int k = 0; k < PERL; ++k) {
+            const uint32_t u = k * static_cast<uint32_t>(rt.threads) + tt;
+            if (u < nlink) {
+                const uint32_t sx = u / LW;
+                const uint32_t e = u - sx * LW;
+                lpre[k] = W[((lstart + sx) * 40 + wb) * L + e];
+            }
+        }
+    };
+    auto at = [&](int xx) __attribute__((always_inline)) {
+        return reinterpret_cast<const S*>(rtile + xx * (rt.units + 1)) + rg * RB;
+    };
+
+    cx<R> acc[RB][NC][4];
+#pragma unroll
+    for (int k = 0; k < RB; ++k)
+#pragma unroll
+        for (int a = 0; a < NC; ++a)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc[k][a][s] = {R(0), R(0)};
+
+    fetch(0);
+    for (int rc = 0; rc < 27; ++rc) {
+        __syncthreads();  // the previous row copy has been consumed
+#pragma unroll
+        for (int k = 0; k < PER; ++k) rtile[slot[k]] = pre[k];
+#pragma unroll
+        for (int k = 0; k < PERL; ++k) {
+            const uint32_t u = k * static_cast<uint32_t>(rt.threads) + tt;
+            if (u < nlink) lwin[u] = lpre[k];
+        }
+        __syncthreads();
+        if (rc < 26) fetch(rc + 1);
+        if (active) {
+            const int iy = rc % 3, iz = (rc / 3) % 3, it = rc / 9;
+            const int kt = it != 1, kyz = (iy != 1) + (iz != 1);
+            const R bsign = (g.apbc && ((it == 0 && ct == 0) || (it == 2 && ct == g.nt - 1))) ? R(-1) : R(1);
+#pragma unroll
+            for (int ix = 0; ix < 3; ++ix) {
+                const int xn = wrap(x + ix - 1, g.nx);
+                const S* nbp = at(xn);
+                if (rc == 13 && ix == 1) {  // the centre: (m - lambda_0 / 2) u(n)
+#pragma unroll
+                    for (int k = 0; k < RB; ++k)
+#pragma unroll
+                        for (int a = 0; a < NC; ++a)
+#pragma unroll
+                            for (int s = 0; s < 4; ++s) {
+                                const cx<R> v = io<R, S>::ld(nbp + (a * 4 + s) * nv + k);
+                                acc[k][a][s].re += diag * v.re;
+                                acc[k][a][s].im += diag * v.im;
+                            }
+                    continue;
+                }
+                // W_d(n): stored at the own site (rc < 13, or rc = 13 with d_x = -1), else the
+                // adjoint of the stored link at n + d
+                cx<R> l[NC][NC];
+                const bool adj = rc > 13 || (rc == 13 && ix == 2);
+                const G* lp = lwin + (adj ? xn : x) * LW + (rc < 13 ? ix : (rc == 13 ? 2 : 2 - ix)) * L;
+                if (!adj) {
+#pragma unroll
+                    for (int a = 0; a < NC; ++a)
+#pragma unroll
+                        for (int b = 0; b < NC; ++b) l[a][b] = io<R, G>::ld(lp + a * NC + b);
+                } else {
+#pragma unroll
+                    for (int a = 0; a < NC; ++a)
+#pragma unroll
+                        for (int b = 0; b < NC; ++b) l[b][a] = cconj(io<R, G>::ld(lp + a * NC + b));
+                }
+                const int kh = kt + kyz + (ix != 1);
+                const R rhok = bsign * static_cast<R>(DAG ? -c_rho[kh] : c_rho[kh]);
+                const R lh = bsign * static_cast<R>(c_halflam[kh]);
+                const R q1 = rhok * (ix - 1), q2 = rhok * (iy - 1), q3 = rhok * (iz - 1), q4 = rhok * (it - 1);
+#pragma unroll
+                for (int k = 0; k < RB; ++k) {
+                    cx<R> p[NC][4];
+#pragma unroll
+                    for (int b = 0; b < NC; ++b)
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) p[b][s] = io<R, S>::ld(nbp + (b * 4 + s) * nv + k);
+#pragma unroll
+                    for (int a = 0; a < NC; ++a) {
+                        cx<R> ch[4] = {{R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}};
+#pragma unroll
+                        for (int b = 0; b < NC; ++b)
+#pragma unroll
+                            for (int s = 0; s < 4; ++s) cfma(ch[s], l[a][b], p[b][s]);
+                        spin_accumulate(acc[k][a], ch, lh, q1, q2, q3, q4, ix != 1, iy != 1, iz != 1, it != 1);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (active) {
+        S* o = const_cast<S*>(at(x));
+#pragma unroll
+        for (int k = 0; k < RB; ++k)
+#pragma unroll
+            for (int a = 0; a < NC; ++a)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) io<R, S>::st(o + (a * 4 + s) * nv + k, acc[k][a][s]);
+    }
+    __syncthreads();
+    u32x4* dst = reinterpret_cast<u32x4*>(out) + own_start * rt.units;
+    const uint32_t total = static_cast<uint32_t>(rt.S) * rt.units;
+    for (uint32_t u = tid; u < total; u += blockDim.x) dst[u] = rtile[u + fast_div(u, rt.magic_units)];
+}
+
+template <int NC, int RB, class P>
+bool launch_rows(const StencilArgs& a, hipStream_t st) {
+    using S = typename P::S;
+    const size_t block_bytes = static_cast<size_t>(NC) * 4 * a.nv * sizeof(S);
+    if (block_bytes % 16 != 0 || !tile_aligned(a)) return false;
+    const int units = static_cast<int>(block_bytes / 16);
+    const int nrg = a.nv / RB;
+    const int64_t rows = a.g.vol / a.g.nx;
+    if (choose_tile_rows(a.variant, rows, a.g.nx, units, nrg) != 1) return false;
+    if (row_tile_lds(a.g.nx, units) > 64 * 1024) return false;
+    // the link window (3 links per site) is staged with at most 4 elements per thread
+    if (static_cast<int64_t>(a.g.nx) * 3 * NC * NC > 4 * static_cast<int64_t>(a.g.nx) * nrg) return false;
+    RowTile rt{};
+    rt.R = 1;
+    rt.S = a.g.nx;
+    rt.nrg = nrg;
+    rt.units = units;
+    rt.row_units = a.g.nx * units;
+    rt.threads = rt.S * nrg;
+    rt.ntiles = rows;
+    rt.magic_nrg = div_magic(nrg);
+    rt.magic_nx = div_magic(a.g.nx);
+    rt.magic_units = div_magic(units);
+    rt.magic_row_units = div_magic(rt.row_units);
+    row_order(4, a.g, rt);
+    const int block = (rt.threads + 63) / 64 * 64;
+    const size_t lds = row_tile_lds(rt.S, units) + static_cast<size_t>(rt.S) * 3 * NC * NC * sizeof(typename P::G);
+    if (lds > 64 * 1024) return false;
+    const dim3 grid(static_cast<unsigned>(grid_blocks_x8(rt.ntiles, 1)));
+    using R = typename P::R;
+    const R diag = static_cast<R>(a.mass + 120.0 / 64.0);
+    auto W = static_cast<const typename P::G*>(a.gauge);
+    auto in = static_cast<const S*>(a.in);
+    auto out = static_cast<S*>(a.out);
+    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, grid, dim3(block), lds, st, W, in, out, diag, a.g, a.nv, rt); };
+    if (a.nv == 12 && RB == 1) {
+        if (a.dagger)
+            go(brillouin_rows_kernel<NC, RB, true, P, 12>);
+        else
+            go(brillouin_rows_kernel<NC, RB, false, P, 12>);
+    } else {
+        if (a.dagger)
+            go(brillouin_rows_kernel<NC, RB, true, P, 0>);
+        else
+            go(brillouin_rows_kernel<NC, RB, false, P, 0>);
+    }
+    return true;
+}
+
 template <int NC, int RB, class P>
 void launch_rb(const StencilArgs& a, hipStream_t st) {
     using R = typename P::R;
+    if (a.variant == 4 && launch_rows<NC, RB, P>(a, st)) return;
     const int block = 256;
     const int64_t threads = a.g.vol * (a.nv / RB);
     const dim3 grid(static_cast<unsigned>(grid_blocks_x8(threads, block)));

@@ -37,7 +37,7 @@ int choose_variant(dirac_op op, dirac_prec prec);
 // with a fixed number of blocks and a fixed summation order; `partial` must hold
 // reduce_partial_doubles(nv) doubles of device scratch.
 // ---------------------------------------------------------------------------
-constexpr int kReduceBlocks = 512;
+constexpr int kReduceBlocks = 2048;
 constexpr int kReduceThreads = 256;
 inline size_t reduce_partial_doubles(int nv) { return static_cast<size_t>(kReduceBlocks) * 2 * nv; }
 

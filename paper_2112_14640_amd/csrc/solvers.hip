@@ -71,12 +71,13 @@ int apply_normal(const OpCtx& o, dirac_prec p, const void* gauge, const void* in
     return apply_op(o, p, gauge, tmp, out, true, st);
 }
 
-// Device scalar kernels (one thread per RHS).
+// Device scalar kernels (one thread per RHS).  alpha = rr / p^+ A p with p^+ A p = ||D p||^2
+// (A = D^+ D), one double per RHS.
 __global__ void k_cg_alpha(const double* __restrict__ pq, const double* __restrict__ rr, const double* __restrict__ mask,
                            double* __restrict__ alpha, int nv) {
     const int i = threadIdx.x;
     if (i >= nv) return;
-    const double d = pq[2 * i];
+    const double d = pq[i];
     const bool ok = mask[i] != 0.0 && d > 0.0 && std::isfinite(d);
     alpha[2 * i] = ok ? rr[i] / d : 0.0;
     alpha[2 * i + 1] = 0.0;
@@ -247,7 +248,8 @@ int cg_core(const OpCtx& o, const CGVecs& v, const Rules& ru, Scalars& s, hipStr
         }
         ++it;
         if ((rc = apply_normal(o, v.pp, v.gauge, v.p, v.q, v.t, st))) return rc;
-        if ((rc = blas_dot(v.pp, v.p, v.pp, v.q, o.nrows, nv, s.partial, s.pq, st))) return rc;
+        // p^+ D^+ D p = ||t||^2 with t = D p: one vector read instead of two
+        if ((rc = blas_norm2(v.pp, v.t, o.nrows, nv, s.partial, s.pq, st))) return rc;
         hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, st, s.pq, s.rr, s.mask, s.alpha, nv);
         if ((rc = fused_r_update(v.pr, v.r, v.pp, v.q, s.alpha, o.nrows, nv, s.partial, s.rr_new, st))) return rc;
         if ((rc = d2h(h, s.rr_new, nv, st))) return rc;
@@ -393,7 +395,7 @@ int cg_reliable(const OpCtx& o, const RUVecs& v, const Rules& ru, double delta, 
         }
         ++it;
         if ((rc = apply_normal(o, v.pin, v.g_lo, v.p, v.q, v.t, st))) return rc;
-        if ((rc = blas_dot(v.pin, v.p, v.pin, v.q, o.nrows, nv, s.partial, s.pq, st))) return rc;
+        if ((rc = blas_norm2(v.pin, v.t, o.nrows, nv, s.partial, s.pq, st))) return rc;  // ||D p||^2
         hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, st, s.pq, s.rr, s.mask, s.alpha, nv);
         if ((rc = fused_r_update(F32, v.r, v.pin, v.q, s.alpha, o.nrows, nv, s.partial, s.rr_new, st))) return rc;
         if ((rc = d2h(h, s.rr_new, nv, st))) return rc;
@@ -849,7 +851,7 @@ int run_solver(int solver, dirac_op op, dirac_prec outer, dirac_prec inner, cons
             rc = bicgstab_core(o, v, ru, s, st, res);
         }
     } else if (solver == 0 && scheme == 0) {
-        const double delta = (opts && opts->delta > 0) ? opts->delta : (inner == DIRAC_BF16 ? 0.5 : 0.1);
+        const double delta = (opts && opts->delta > 0) ? opts->delta : 0.1;
         RUVecs v;
         v.b = b;
         v.x = x;

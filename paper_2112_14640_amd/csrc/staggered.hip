@@ -243,9 +243,209 @@ bool launch_lds(const StencilArgs& a, hipStream_t st) {
     return true;
 }
 
+
+// Row-tiled variant: one x-row (every RHS) per work-group, the rows one step along +-y, +-z,
+// +-t staged in LDS one at a time with contiguous loads of Unit (16 or 8 bytes), the next row copy
+// and its link in flight while the current direction is consumed (see the Wilson row kernel).
+template <int NC, int RB, bool DAG, class P, typename Unit>
+__global__ __launch_bounds__(512) void staggered_rows_kernel(const typename P::G* __restrict__ U,
+                                                             const typename P::S* __restrict__ in,
+                                                             typename P::S* __restrict__ out, typename P::R mass,
+                                                             Geom g, int nv, RowTile rt) {
+    using R = typename P::R;
+    using S = typename P::S;
+    using G = typename P::G;
+    constexpr int PER = NC * RB * static_cast<int>(sizeof(S)) / static_cast<int>(sizeof(Unit));
+    constexpr int L = NC * NC;
+    extern __shared__ __align__(16) unsigned char sraw[];
+    Unit* rtile = reinterpret_cast<Unit*>(sraw);
+
+    const int64_t tix = logical_block();
+    if (tix >= rt.ntiles) return;
+    const uint32_t rho = tile_row(static_cast<uint32_t>(tix), rt, g);
+    const uint32_t tid = threadIdx.x;
+    const bool active = tid < static_cast<uint32_t>(rt.threads);
+    const uint32_t tt = active ? tid : tid - rt.threads;
+    const uint32_t j = fast_div(tt, rt.magic_nrg);
+    const int rg = static_cast<int>(tt - j * rt.nrg);
+    const int x = static_cast<int>(j);
+    const int64_t rowsite = static_cast<int64_t>(rho) * g.nx;
+    const int64_t site = rowsite + x;
+    int cy, cz, ct;
+    {
+        const uint32_t q = rho / static_cast<uint32_t>(g.ny);
+        cy = static_cast<int>(rho - q * g.ny);
+        const uint32_t q2 = q / static_cast<uint32_t>(g.nz);
+        cz = static_cast<int>(q - q2 * g.nz);
+        ct = static_cast<int>(q2);
+    }
+    const Unit* src = reinterpret_cast<const Unit*>(in);
+    uint32_t slot[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const uint32_t u = k * static_cast<uint32_t>(rt.threads) + tt;
+        slot[k] = u + fast_div(u, rt.magic_units);
+    }
+    Unit pre[PER];
+    auto fetch = [&](int64_t row_start) __attribute__((always_inline)) {
+        const Unit* p = src + row_start * rt.units + tt;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) pre[k] = p[static_cast<int64_t>(k) * rt.threads];
+    };
+    auto stash = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) rtile[slot[k]] = pre[k];
+    };
+    auto at = [&](uint32_t jj) __attribute__((always_inline)) {
+        return reinterpret_cast<const S*>(rtile + jj * (rt.units + 1)) + rg * RB;
+    };
+    auto load_link = [&](cx<R> (&l)[NC][NC], const G* lp, bool adj) __attribute__((always_inline)) {
+#pragma unroll
+        for (int a = 0; a < NC; ++a)
+#pragma unroll
+            for (int b = 0; b < NC; ++b) {
+                const cx<R> v = io<R, G>::ld(lp + a * NC + b);
+                if (adj)
+                    l[b][a] = cconj(v);
+                else
+                    l[a][b] = v;
+            }
+    };
+    cx<R> acc[RB][NC];
+    const R half = DAG ? R(-0.5) : R(0.5);
+    // eta_mu(n) = (-1)^(x_0 + ... + x_{mu-1})
+    const R eta[4] = {half, (x & 1) ? -half : half, ((x + cy) & 1) ? -half : half,
+                      ((x + cy + cz) & 1) ? -half : half};
+    const int xp = x + 1 == g.nx ? 0 : x + 1;
+    const int xm = x == 0 ? g.nx - 1 : x - 1;
+    cx<R> lxp[NC][NC], lxm[NC][NC], lnext[NC][NC];
+    fetch(rowsite);
+    load_link(lxp, U + (site * 4 + 0) * L, false);
+    load_link(lxm, U + ((rowsite + xm) * 4 + 0) * L, true);
+    stash();
+    __syncthreads();
+    fetch(row_neighbour_start(rho, 0, g));
+    load_link(lnext, U + (site * 4 + 1) * L, false);
+    auto hop_acc = [&](const cx<R> (&l)[NC][NC], const S* nb, R scale) __attribute__((always_inline)) {
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            cx<R> p[NC];
+#pragma unroll
+            for (int b = 0; b < NC; ++b) p[b] = cscale(scale, io<R, S>::ld(nb + b * nv + k));
+#pragma unroll
+            for (int a = 0; a < NC; ++a)
+#pragma unroll
+                for (int b = 0; b < NC; ++b) cfma(acc[k][a], l[a][b], p[b]);
+        }
+    };
+    if (active) {
+        const S* mine = at(j);
+#pragma unroll
+        for (int k = 0; k < RB; ++k)
+#pragma unroll
+            for (int a = 0; a < NC; ++a) acc[k][a] = cscale(mass, io<R, S>::ld(mine + a * nv + k));
+        hop_acc(lxp, at(xp), eta[0]);
+        hop_acc(lxm, at(xm), -eta[0]);
+    }
+    auto step = [&](auto mu_c, auto back_c) __attribute__((always_inline)) {
+        constexpr int MU = decltype(mu_c)::value;
+        constexpr bool BACK = decltype(back_c)::value;
+        constexpr int DIR = 2 * (MU - 1) + (BACK ? 1 : 0);
+        cx<R> lcur[NC][NC];
+#pragma unroll
+        for (int a = 0; a < NC; ++a)
+#pragma unroll
+            for (int b = 0; b < NC; ++b) lcur[a][b] = lnext[a][b];
+        __syncthreads();
+        stash();
+        __syncthreads();
+        if constexpr (DIR < 5) {
+            constexpr int ND = DIR + 1;
+            constexpr int NMU = ND / 2 + 1;
+            const int64_t nrow = row_neighbour_start(rho, ND, g);
+            fetch(nrow);
+            if constexpr (ND % 2 == 0)
+                load_link(lnext, U + (site * 4 + NMU) * L, false);
+            else
+                load_link(lnext, U + ((nrow + x) * 4 + NMU) * L, true);
+        }
+        if (active) {
+            R sc = BACK ? -eta[MU] : eta[MU];
+            if (MU == 3 && g.apbc && ct == (BACK ? 0 : g.nt - 1)) sc = -sc;  // fermion sign
+            hop_acc(lcur, at(j), sc);
+        }
+    };
+    step(std::integral_constant<int, 1>{}, std::false_type{});
+    step(std::integral_constant<int, 1>{}, std::true_type{});
+    step(std::integral_constant<int, 2>{}, std::false_type{});
+    step(std::integral_constant<int, 2>{}, std::true_type{});
+    step(std::integral_constant<int, 3>{}, std::false_type{});
+    step(std::integral_constant<int, 3>{}, std::true_type{});
+    __syncthreads();
+    if (active) {
+        S* o = const_cast<S*>(at(j));
+#pragma unroll
+        for (int k = 0; k < RB; ++k)
+#pragma unroll
+            for (int a = 0; a < NC; ++a) io<R, S>::st(o + a * nv + k, acc[k][a]);
+    }
+    __syncthreads();
+    Unit* dst = reinterpret_cast<Unit*>(out) + rowsite * rt.units;
+    const uint32_t total = static_cast<uint32_t>(rt.S) * rt.units;
+    for (uint32_t u = tid; u < total; u += blockDim.x) dst[u] = rtile[u + fast_div(u, rt.magic_units)];
+}
+
+template <int NC, int RB, class P>
+bool launch_rows(const StencilArgs& a, hipStream_t st) {
+    using S = typename P::S;
+    constexpr size_t share = static_cast<size_t>(NC) * RB * sizeof(S);  // bytes per thread per row copy
+    constexpr size_t ub = share % 16 == 0 ? 16 : (share % 8 == 0 ? 8 : 0);
+    if constexpr (ub == 0) {
+        return false;
+    } else {
+        using Unit = std::conditional_t<ub == 16, u32x4, u32x2>;
+        const size_t block_bytes = static_cast<size_t>(NC) * a.nv * sizeof(S);
+        if (block_bytes % ub != 0 || !tile_aligned(a)) return false;
+        const int units = static_cast<int>(block_bytes / ub);
+        const int nrg = a.nv / RB;
+        const int64_t rows = a.g.vol / a.g.nx;
+        const int64_t threads = static_cast<int64_t>(a.g.nx) * nrg;
+        const size_t lds = static_cast<size_t>(a.g.nx) * (units + 1) * ub;
+        if (threads < 64 || threads > 512 || lds > 64 * 1024) return false;
+        RowTile rt{};
+        rt.R = 1;
+        rt.S = a.g.nx;
+        rt.nrg = nrg;
+        rt.units = units;
+        rt.row_units = a.g.nx * units;
+        rt.threads = static_cast<int>(threads);
+        rt.ntiles = rows;
+        rt.magic_nrg = div_magic(nrg);
+        rt.magic_nx = div_magic(a.g.nx);
+        rt.magic_units = div_magic(units);
+        rt.magic_row_units = div_magic(rt.row_units);
+        row_order(4, a.g, rt);
+        const int block = (rt.threads + 63) / 64 * 64;
+        const dim3 grid(static_cast<unsigned>(grid_blocks_x8(rt.ntiles, 1)));
+        using R = typename P::R;
+        const R m = static_cast<R>(a.mass);
+        auto U = static_cast<const typename P::G*>(a.gauge);
+        auto in = static_cast<const S*>(a.in);
+        auto out = static_cast<S*>(a.out);
+        if (a.dagger)
+            hipLaunchKernelGGL((staggered_rows_kernel<NC, RB, true, P, Unit>), grid, dim3(block), lds, st, U, in, out,
+                               m, a.g, a.nv, rt);
+        else
+            hipLaunchKernelGGL((staggered_rows_kernel<NC, RB, false, P, Unit>), grid, dim3(block), lds, st, U, in,
+                               out, m, a.g, a.nv, rt);
+        return true;
+    }
+}
+
 template <int NC, int RB, class P>
 void launch_rb(const StencilArgs& a, hipStream_t st) {
     using R = typename P::R;
+    if (a.variant == 4 && launch_rows<NC, RB, P>(a, st)) return;
     if (use_lds_variant(a, false) && launch_lds<NC, RB, P>(a, st)) return;
     const int block = 256;
     const int64_t threads = a.g.vol * (a.nv / RB);

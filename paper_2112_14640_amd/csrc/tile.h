@@ -162,6 +162,17 @@ __device__ __forceinline__ int64_t row_neighbour_start(uint32_t rho, int dir, co
     return ((static_cast<int64_t>(t) * g.nz + z) * g.ny + y) * g.nx;
 }
 
+// 16- and 8-byte units of the row copies (native vector types, so register arrays of them stay
+// in registers).
+using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
+using u32x2 = unsigned int __attribute__((ext_vector_type(2)));
+
+// 16-byte units each thread moves per row copy of a four-spin field: its share of the row.
+template <int NC, int RB, class P>
+struct RowUnits {
+    static constexpr int PER = NC * 4 * RB * static_cast<int>(sizeof(typename P::S)) / 16;
+};
+
 // Bytes of LDS for one staged row tile (site stride padded by one 16-byte unit).
 inline size_t row_tile_lds(int S, int units) { return static_cast<size_t>(S) * (units + 1) * 16; }
 
@@ -208,12 +219,34 @@ inline void row_order(int variant, const Geom& g, RowTile& rt) {
     rt.nby = g.ny / rt.by;
 }
 
-// Row tiles are used for variants 4..7 when one row of every RHS fits: at most 512 threads
-// and 64 KiB of LDS.  Returns the rows per tile (1) or 0.
+// LDS a work-group may request on the current device (64 KiB unless the device reports more;
+// above 64 KiB a kernel must opt in with hipFuncAttributeMaxDynamicSharedMemorySize).
+inline size_t max_lds_per_block() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v < 65536)
+        return 65536;
+    return static_cast<size_t>(v);
+}
+
+// Largest row tile taken: 96 KiB of LDS (two work-groups per 160 KiB CU).
+constexpr size_t kRowLdsCap = 96 * 1024;
+
+// Row tiles are used for variants 4..7 when one row of every RHS fits: 64..512 threads and at
+// most kRowLdsCap bytes of LDS (and what the device allows).  Returns the rows per tile (1) or 0.
 inline int choose_tile_rows(int, int64_t rows, int nx, int units, int nrg) {
     const int64_t threads = static_cast<int64_t>(nx) * nrg;
-    if (rows >= 1 && threads >= 64 && threads <= 512 && row_tile_lds(nx, units) <= 64 * 1024) return 1;
+    const size_t lds = row_tile_lds(nx, units);
+    if (rows >= 1 && threads >= 64 && threads <= 512 && lds <= kRowLdsCap && lds <= max_lds_per_block()) return 1;
     return 0;
+}
+
+// Opt a row kernel in to more than 64 KiB of dynamic LDS (once per kernel); false if refused.
+template <typename K>
+bool allow_lds(K kernel, size_t lds) {
+    if (lds <= 64 * 1024) return true;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               static_cast<int>(kRowLdsCap)) == hipSuccess;
 }
 
 // The LDS-staged tiles are used when variant 2 is selected (see choose_variant).

@@ -428,13 +428,6 @@ __global__ __launch_bounds__(512) void wilson_lds_kernel(const typename P::G* __
 // direction is issued into registers before the current direction is consumed from LDS, so the
 // loads of one direction overlap the arithmetic of the previous one.  The output tile leaves
 // through LDS as one contiguous store.
-template <int NC, int RB, class P>
-struct RowUnits {
-    // 16-byte units each thread moves per row copy: its share of the tile
-    static constexpr int PER = NC * 4 * RB * static_cast<int>(sizeof(typename P::S)) / 16;
-};
-
-using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
 
 template <int NC, int RB, bool DAG, class P, int NVC, bool UNSCALED>
 __global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* __restrict__ U,
@@ -605,7 +598,15 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
     auto U = static_cast<const typename P::G*>(a.gauge);
     auto in = static_cast<const S*>(a.in);
     auto out = static_cast<S*>(a.out);
-    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, grid, dim3(block), lds, st, U, in, out, diag, a.g, a.nv, rt); };
+    bool ok = true;
+    auto go = [&](auto kern) {
+        static const bool allowed = allow_lds(kern, kRowLdsCap);
+        if (!allowed && lds > 64 * 1024) {
+            ok = false;
+            return;
+        }
+        hipLaunchKernelGGL(kern, grid, dim3(block), lds, st, U, in, out, diag, a.g, a.nv, rt);
+    };
     if (a.variant == 5) {  // per-hop scaling, runtime RHS stride
         if (a.dagger)
             go(wilson_rows_kernel<NC, RB, true, P, 0, false>);
@@ -622,7 +623,7 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
         else
             go(wilson_rows_kernel<NC, RB, false, P, 0, true>);
     }
-    return true;
+    return ok;
 }
 
 template <int NC, int RB, class P>

@@ -1,0 +1,115 @@
+"""HBM traffic of the six stencil launches of bench.py from two rocprofv3 counter runs.
+
+    python -m paper_2112_14640_amd.traffic FETCH_DIR WRITE_DIR [--out-json profiles/traffic.json]
+                                          [--out-txt profiles/<name>.txt]
+
+FETCH_DIR and WRITE_DIR are the output directories of
+
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d FETCH_DIR -o bench -- \
+        python3 bench.py --steps 3 --warmup 1 --no-cg --no-cpu --copy-calibration
+    rocprofv3 --pmc WRITE_SIZE --output-format csv -d WRITE_DIR -o bench -- (same command)
+
+Both counters are in KiB per dispatch.  Each is scaled by the ratio of the bytes a 512 MiB
+device copy (``--copy-calibration``: torch's copy_, run as __amd_rocclr_copyBuffer) moves to the
+value the same counter reads for that copy.  The JSON records, per launch, the scaled bytes next
+to the algorithmic bytes and a hash of the kernel sources; bench.py reports the traffic only while
+the sources still hash to it.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+COPY_BYTES = 512 * 2 ** 20
+SOURCES = {
+    "wilson": "paper_2112_14640_amd/csrc/wilson.hip",
+    "staggered": "paper_2112_14640_amd/csrc/staggered.hip",
+    "brillouin": "paper_2112_14640_amd/csrc/brillouin.hip",
+}
+COMMON = ["paper_2112_14640_amd/csrc/common.h", "paper_2112_14640_amd/csrc/tile.h",
+          "paper_2112_14640_amd/csrc/api.hip"]
+KERNEL = re.compile(r"(wilson|staggered|brillouin)\w*kernel<\d+, \d+, (true|false)")
+
+
+def source_hash(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_means(root, counter):
+    """{launch key or 'copy': mean KiB per dispatch} for one counter run."""
+    agg = collections.defaultdict(list)
+    for f in glob.glob(os.path.join(root, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] != counter:
+                continue
+            name = r["Kernel_Name"]
+            if "copyBuffer" in name:
+                key = "copy"
+            else:
+                m = KERNEL.search(name)
+                if not m:
+                    continue
+                key = m.group(1) + ("_dagger" if m.group(2) == "true" else "")
+            agg[key].append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in agg.items()}
+
+
+def algorithmic_bytes(op, dims=(16, 16, 16, 32), nc=3, nv=12, w_s=4, w_g=4):
+    """Compulsory bytes of one FP32 apply: input read once, output written once, links read once."""
+    vol = dims[0] * dims[1] * dims[2] * dims[3]
+    spin = 1 if op == "staggered" else 4
+    dirs = 40 if op == "brillouin" else 4
+    return vol * (2 * (2 * nc * spin * nv) * w_s + dirs * 2 * nc * nc * w_g)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("fetch_dir")
+    ap.add_argument("write_dir")
+    ap.add_argument("--out-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--out-txt", default=None)
+    a = ap.parse_args()
+    fetch = counter_means(a.fetch_dir, "FETCH_SIZE")
+    write = counter_means(a.write_dir, "WRITE_SIZE")
+    f_scale = COPY_BYTES / (fetch["copy"] * 1024)
+    w_scale = COPY_BYTES / (write["copy"] * 1024)
+    table = {"_about": ("HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch), "
+                        f"each scaled by the ratio of a 512 MiB device copy's known bytes to the same counter's reading "
+                        f"for that copy (FETCH x{f_scale:.4f}, WRITE x{w_scale:.4f}); valid while the listed sources "
+                        "hash to source_hash")}
+    lines = []
+    for key in ("wilson", "wilson_dagger", "brillouin", "brillouin_dagger", "staggered", "staggered_dagger"):
+        if key not in fetch or key not in write:
+            continue
+        op = key.split("_")[0]
+        fb = fetch[key] * 1024 * f_scale
+        wb = write[key] * 1024 * w_scale
+        alg = algorithmic_bytes(op)
+        srcs = [SOURCES[op]] + COMMON
+        table[f"{key}_fp32_16x32_nv12"] = {
+            "bytes_per_launch": int(round(fb + wb)), "fetch_bytes": int(round(fb)), "write_bytes": int(round(wb)),
+            "algorithmic_bytes": alg, "sources": srcs, "source_hash": source_hash(srcs)}
+        lines.append(f"{key:18s} fetch {fb / 1e6:8.1f} MB  write {wb / 1e6:7.1f} MB  total {(fb + wb) / 1e6:8.1f} MB  "
+                     f"algorithmic {alg / 1e6:7.1f} MB  ratio {(fb + wb) / alg:.2f}")
+    with open(a.out_json, "w") as f:
+        json.dump(table, f, indent=1)
+    text = [f"# scale: FETCH x{f_scale:.4f}, WRITE x{w_scale:.4f} (512 MiB copy calibration)"] + lines
+    if a.out_txt:
+        with open(a.out_txt, "w") as f:
+            f.write("\n".join(text) + "\n")
+    print("\n".join(text))
+
+
+if __name__ == "__main__":
+    main()

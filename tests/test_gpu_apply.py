@@ -232,6 +232,59 @@ def test_wilson_row_tiles(case, prec, variant):
             dirac.set_launch_shape("wilson", prec, 0, 0)
 
 
+BRILLOUIN_ROW_CASES = [
+    # dims, nc, nv, antiperiodic: rows of 6, 8 and 7 sites (at least 64 threads per row); the last
+    # case does not fit a row tile (a site block of 56 bytes) and takes the direct kernel
+    ((6, 4, 4, 6), 3, 12, True),
+    ((8, 2, 6, 4), 2, 8, False),
+    ((7, 2, 2, 4), 3, 12, True),
+    ((6, 2, 2, 4), 4, 12, True),
+    ((4, 4, 2, 2), 1, 7, True),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("case", range(len(BRILLOUIN_ROW_CASES)))
+def test_brillouin_row_tiles(case, prec):
+    """The row-tiled Brillouin kernel (27 row copies with link windows in LDS) against the oracle."""
+    dims, nc, nv, apbc = BRILLOUIN_ROW_CASES[case]
+    gauge, u = _inputs("brillouin", dims, nc, nv, seed=60 + case)
+    try:
+        dirac.set_launch_shape("brillouin", prec, 1, 4)
+        for dagger in (False, True):
+            v, g_in, u_in = _run("brillouin", prec, gauge, u, 0.04, apbc, dagger)
+            err = col_rel_err(v, ORACLE[("brillouin", dagger)](g_in, u_in, 0.04, apbc))
+            assert err < TOL[prec], (dims, nc, nv, dagger, err)
+    finally:
+        dirac.set_launch_shape("brillouin", prec, 0, 0)
+
+
+STAGGERED_ROW_CASES = [
+    # dims (even), nc, nv, antiperiodic: rows of 8 and 16 sites, 64..192 threads per row
+    ((8, 4, 4, 6), 3, 12, True),
+    ((16, 2, 2, 4), 3, 12, True),
+    ((8, 2, 2, 4), 2, 8, False),
+    ((8, 2, 2, 2), 4, 12, True),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("case", range(len(STAGGERED_ROW_CASES)))
+def test_staggered_row_tiles(case, prec):
+    """The row-tiled staggered kernel (1 and 2 RHS per thread, where a row fits) against the oracle."""
+    dims, nc, nv, apbc = STAGGERED_ROW_CASES[case]
+    gauge, u = _inputs("staggered", dims, nc, nv, seed=80 + case)
+    for rb in (1, 2):
+        try:
+            dirac.set_launch_shape("staggered", prec, rb, 4)
+            for dagger in (False, True):
+                v, g_in, u_in = _run("staggered", prec, gauge, u, 0.06, apbc, dagger)
+                err = col_rel_err(v, ORACLE[("staggered", dagger)](g_in, u_in, 0.06, apbc))
+                assert err < TOL[prec], (dims, nc, nv, rb, dagger, err)
+        finally:
+            dirac.set_launch_shape("staggered", prec, 0, 0)
+
+
 def test_invalid_arguments_raise():
     U = torch.zeros((4, 4, 4, 4, 4, 3, 3), dtype=torch.complex64, device="cuda:0")
     u = torch.zeros((4, 4, 4, 4, 3, 4, 2), dtype=torch.complex64, device="cuda:0")
