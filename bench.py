@@ -11,9 +11,12 @@ time.  Four input sets are rotated so that consecutive launches do not find thei
 in the 256 MB Infinity Cache.
 
 Also reported (outside the timed steps): per-kernel durations and rooflines from HIP events
-on the launch stream, the Brillouin link build, the mixed-precision vs FP64 CG time-to-solution
+on the launch stream (against the published peaks and against the device's measured copy and
+FMA ceilings), the Brillouin link build, the same applies at the large sizes (Wilson 32^3 x 64,
+staggered and Brillouin 48^3 x 96, Haar links), the mixed-precision vs FP64 CG time-to-solution
 on D_W^dag D_W at 32^3 x 64 (Nv = 12, exp(i 0.5 H) links, m = 0.01, true FP64 relative residual
-1e-10), and the FP64 NumPy oracle timed on the host on a bounded sample (12^3 x 24, same Nc, Nv).
+1e-10), BiCGstab on D_B at 32^3 x 64 (mixed FP64/FP32 and plain FP64, to 1e-8), and the FP64
+NumPy oracle timed on the host on a bounded sample (12^3 x 24, same Nc, Nv).
 Progress goes to stderr; stdout carries exactly one JSON line.
 """
 from __future__ import annotations
@@ -161,6 +164,130 @@ def run_applies(args, torch, dirac, si):
                 link_build_ms=round(min(link_ms), 3), dims=dims, nc=nc, nv=nv)
 
 
+def run_ceilings(torch, dirac):
+    """The device's sustained copy bandwidth and non-packed FMA rates (the measured roofline denominators)."""
+    n = 2 ** 30 // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    copy = dirac.probe_copy(src, dst, reps=10)
+    del src, dst
+    torch.cuda.empty_cache()
+    out = {"copy_GBps": round(copy / 1e9, 1), "fp32_fma_TFLOPs": round(dirac.probe_fma("fp32") / 1e12, 2),
+           "fp64_fma_TFLOPs": round(dirac.probe_fma("fp64") / 1e12, 2),
+           "how": "dirac_probe_copy: 1 GiB device copy, 16 B per lane, 10 launches; dirac_probe_fma: 16 independent "
+                  "non-packed FMA chains per thread, 16 work-groups of 256 threads per CU"}
+    log(f"[bench] ceilings: copy {out['copy_GBps']} GB/s, FMA fp32 {out['fp32_fma_TFLOPs']} / fp64 "
+        f"{out['fp64_fma_TFLOPs']} TFLOP/s")
+    return out
+
+
+def time_apply(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def run_scale(torch, dirac, si, ceil):
+    """The applies at the large sizes (Haar links, m = 0.05, Nc = 3, Nv = 12, FP32), far above the caches."""
+    dev = "cuda:0"
+    nc, nv, m = 3, 12, 0.05
+    out = {}
+    gen = torch.Generator(device=dev)
+
+    def report(name, op, dims, ms):
+        vol = dims[0] * dims[1] * dims[2] * dims[3]
+        alg = bytes_per_site(op, nc, nv, 4, 4) * vol
+        flops = dirac.flops_per_site(op, nc) * vol * nv
+        r = {"lattice": list(dims), "ms": round(ms, 3), "gflops": round(flops / (ms * 1e-3) / 1e9, 1)}
+        if op == "brillouin":
+            tf = flops / (ms * 1e-3) / 1e12
+            r.update(bound="alu", achieved=round(tf, 2), unit="TFLOP/s", frac=round(tf / FP32_VECTOR_PEAK_TFS, 4))
+            if ceil:
+                r["frac_of_measured"] = round(tf / ceil["fp32_fma_TFLOPs"], 4)
+        else:
+            gb = alg / (ms * 1e-3) / 1e9
+            r.update(bound="hbm", achieved=round(gb, 1), unit="GB/s", frac=round(gb / HBM_PEAK_GBS, 4))
+            if ceil:
+                r["frac_of_measured"] = round(gb / ceil["copy_GBps"], 4)
+        out[name] = r
+        log(f"[bench] scale {name}: {ms:.3f} ms, {r['achieved']} {r['unit']}")
+
+    # Wilson at 32^3 x 64: two rotated sets (5 GB of spinors)
+    dims = (32, 32, 32, 64)
+    nx, ny, nz, nt = dims
+    sets = []
+    for k in range(2):
+        gen.manual_seed(2000 + k)
+        U = si.haar_su_n_t(gen, (nt, nz, ny, nx, 4), nc, dev, torch.complex64)
+        u = si.complex_gaussian_t(gen, (nt, nz, ny, nx, nc, 4, nv), dev, torch.complex64)
+        sets.append((U, u, torch.empty_like(u)))
+    it = [0]
+
+    def w():
+        U, u, v = sets[it[0] % 2]
+        it[0] += 1
+        dirac.apply("wilson", U, u, m, out=v)
+    report("wilson_32x64", "wilson", dims, time_apply(torch, w, 20))
+    del sets
+    torch.cuda.empty_cache()
+    # staggered and Brillouin at 48^3 x 96
+    dims = (48, 48, 48, 96)
+    nx, ny, nz, nt = dims
+    gen.manual_seed(2100)
+    U = si.haar_su_n_t(gen, (nt, nz, ny, nx, 4), nc, dev, torch.complex64)
+    phi = si.complex_gaussian_t(gen, (nt, nz, ny, nx, nc, nv), dev, torch.complex64)
+    vs = torch.empty_like(phi)
+    report("staggered_48x96", "staggered", dims, time_apply(torch, lambda: dirac.apply("staggered", U, phi, m, out=vs), 10))
+    del phi, vs
+    W = dirac.brillouin_links(U)
+    del U
+    torch.cuda.empty_cache()
+    psi = si.complex_gaussian_t(gen, (nt, nz, ny, nx, nc, 4, nv), dev, torch.complex64)
+    vb = torch.empty_like(psi)
+    report("brillouin_48x96", "brillouin", dims, time_apply(torch, lambda: dirac.apply("brillouin", W, psi, m, out=vb), 4))
+    del W, psi, vb
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_bicgstab(torch, dirac, si):
+    """BiCGstab on D_B at 32^3 x 64 (Haar links, m = 0.05, Nv = 12): FP64-outer/FP32-inner and plain FP64 to 1e-8."""
+    dev = "cuda:0"
+    dims, nc, nv, m = (32, 32, 32, 64), 3, 12, 0.05
+    nx, ny, nz, nt = dims
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(2200)
+    U = si.haar_su_n_t(gen, (nt, nz, ny, nx, 4), nc, dev, torch.complex128)
+    W64 = dirac.brillouin_links(U)
+    del U
+    W32 = W64.to(torch.complex64)
+    b = si.complex_gaussian_t(gen, (nt, nz, ny, nx, nc, 4, nv), dev, torch.complex128)
+    out = {"workload": f"BiCGstab on D_B, {nx}x{ny}x{nz}x{nt}, Nc={nc}, Nv={nv}, Haar links, m={m}, tol=1e-8"}
+    for name, inner in (("fp64", None), ("mixed_fp32", "fp32")):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x, info = dirac.bicgstab("brillouin", W64, b, m, tol=1e-8, maxit=3000, inner=inner,
+                                 gauge_lo=W32 if inner else None)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        out[name] = {"seconds": round(dt, 3), "iterations": info.iterations, "outer_iterations": info.outer_iterations,
+                     "reason": info.reason, "max_true_relres": max(info.true_relres)}
+        log(f"[bench] bicgstab {name}: {dt:.2f} s, {info.iterations} it, {info.reason}")
+        del x
+        torch.cuda.empty_cache()
+    if out["mixed_fp32"]["reason"] == "converged":
+        out["mixed_fp32"]["speedup_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed_fp32"]["seconds"], 3)
+    del W64, W32, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_cg(torch, dirac, si):
     """Mixed-precision vs FP64 CG on D_W^dag D_W at 32^3 x 64, Nv = 12, to a true residual 1e-10."""
     dev = "cuda:0"
@@ -233,6 +360,7 @@ def main():
     ap.add_argument("--sets", type=int, default=4)
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-scale", action="store_true", help="skip the large-lattice applies, BiCGstab and ceilings")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (outside the timed steps) whose HBM counters "
                          "scale the PMC byte counts of the stencil kernels")
@@ -256,8 +384,15 @@ def main():
         torch.cuda.synchronize()
         log("[bench] calibration copies done: 5 x 512 MiB read + 512 MiB write")
         del src, dst
+    ceil = None if args.no_scale else run_ceilings(torch, dirac)
     res = run_applies(args, torch, dirac, si)
+    if ceil:
+        for name, r in res["rooflines"].items():
+            r["frac_of_measured"] = round(r["achieved"] / (ceil["fp32_fma_TFLOPs"] if r["bound"] == "alu"
+                                                           else ceil["copy_GBps"]), 4)
+    scale = None if args.no_scale else run_scale(torch, dirac, si, ceil)
     cg = None if args.no_cg else run_cg(torch, dirac, si)
+    bicg = None if (args.no_cg or args.no_scale) else run_bicgstab(torch, dirac, si)
     cpu = None if args.no_cpu else run_cpu_baseline(si)
     nx, ny, nz, nt = res["dims"]
     rl = dict(res["rooflines"][res["dominant"]])
@@ -277,11 +412,15 @@ def main():
         "config": {"workload": f"Wilson, Brillouin and staggered applies and adjoints, {nx}x{ny}x{nz}x{nt}, "
                                f"Nc={res['nc']}, Nv={res['nv']}, FP32, exp(i 0.3 H) links, m=0.05",
                    "lattice": [nx, ny, nz, nt], "nc": res["nc"], "nv": res["nv"], "input_sets_rotated": args.sets},
-        "roofline": {k: rl[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
+        "roofline": {k: rl[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic", "frac_of_measured")
+                     if k in rl},
         "roofline_kernel": res["dominant"],
         "kernels": res["rooflines"],
         "brillouin_link_build_ms": res["link_build_ms"],
+        "ceilings": ceil,
+        "scale": scale,
         "cg": cg,
+        "bicgstab": bicg,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -26,6 +26,7 @@ from . import _lib as L
 
 OPS = {"wilson": L.WILSON, "brillouin": L.BRILLOUIN, "staggered": L.STAGGERED}
 PREC_NAMES = {L.FP64: "fp64", L.FP32: "fp32", L.BF16: "bf16"}
+_PRECS = {v: k for k, v in PREC_NAMES.items()}
 
 
 def _op(op) -> int:
@@ -390,6 +391,27 @@ def bicgstab(op, gauge, b, mass, x0=None, tol=1e-10, maxit=1000, inner=None, gau
                   opts)
 
 
+def probe_copy(src: torch.Tensor, dst: torch.Tensor, reps: int = 10) -> float:
+    """Sustained device copy rate (read + written bytes per second) over src -> dst (same byte size)."""
+    _require(src, "src")
+    _require(dst, "dst")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("probe_copy: src and dst must have the same byte size")
+    out = C.c_double(0.0)
+    L.check(L.load().dirac_probe_copy(_ptr(src), _ptr(dst), nbytes, reps, C.byref(out), _stream()), "dirac_probe_copy")
+    return out.value
+
+
+def probe_fma(prec="fp32") -> float:
+    """Sustained non-packed FMA rate of the device in flop per second (FP32 or FP64)."""
+    p = _PRECS[prec] if isinstance(prec, str) else int(prec)
+    sink = torch.zeros(2, dtype=torch.float64, device=torch.cuda.current_device())
+    out = C.c_double(0.0)
+    L.check(L.load().dirac_probe_fma(p, _ptr(sink), C.byref(out), _stream()), "dirac_probe_fma")
+    return out.value
+
+
 def flops_per_site(op, nc: int) -> float:
     """App. E flop count per site and RHS of one apply."""
     return L.load().dirac_flops_per_site(_op(op), nc)
@@ -397,7 +419,8 @@ def flops_per_site(op, nc: int) -> float:
 
 def set_launch_shape(op, prec, rb: int = 0, variant: int = 0):
     """Launch-shape knob of the stencil kernels: RHS per thread (0 = automatic) and variant
-    (0 = automatic, 1 = direct global loads, 2 = LDS-staged site tiles)."""
+    (0 = automatic, 1 = direct global loads, 2 = LDS-staged site tiles, 3 = direct loads one hop per
+    iteration, 4..7 = row tiles; see include/dirac.h)."""
     if isinstance(prec, str):
         prec = {"fp64": L.FP64, "fp32": L.FP32, "bf16": L.BF16}[prec]
     L.check(L.load().dirac_set_launch_shape(_op(op), prec, rb, variant), "set_launch_shape")

@@ -84,3 +84,17 @@ def test_gamma5_and_epsilon():
     t, z, y, x = np.meshgrid(np.arange(nt), np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     eps = np.where((x + y + z + t) % 2 == 0, 1.0, -1.0)[..., None, None]
     np.testing.assert_array_equal(host(dirac.gamma5("staggered", to_dev(phi))), phi * eps)
+
+
+def test_measurement_probes():
+    """The copy and FMA probes return sane, finite rates and copy the data."""
+    src = torch.randn(2 ** 22, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    bw = dirac.probe_copy(src, dst, reps=3)
+    assert torch.equal(src, dst)
+    assert 1e11 < bw < 2e13, bw
+    for prec in ("fp32", "fp64"):
+        f = dirac.probe_fma(prec)
+        assert 1e12 < f < 4e14, (prec, f)
+    with pytest.raises(Exception):
+        dirac.probe_copy(src, dst[:-1])
