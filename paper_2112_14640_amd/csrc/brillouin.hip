@@ -12,6 +12,7 @@
 // which is Eq. app_bril with the derivative factor of Eq. def_ider written out; the adjoint
 // negates the rho part (g_5-hermiticity).  In the chiral basis sum_mu c_mu g_mu is
 // [[0, B], [B^+, 0]] with B = [[c4 - i c3, -c2 - i c1], [c2 - i c1, c4 + i c3]] (App. C).
+#include <mutex>
 #include <type_traits>
 
 #include "common.h"
@@ -24,6 +25,25 @@ namespace {
 
 __constant__ double c_rho[5] = {0.0, 64.0 / 432.0, 16.0 / 432.0, 4.0 / 432.0, 1.0 / 432.0};
 __constant__ double c_halflam[5] = {-120.0 / 64.0, 4.0 / 64.0, 2.0 / 64.0, 1.0 / 64.0, 0.5 / 64.0};
+
+// Spin-factor scalars per direction, filled once per device from the two tables above:
+// c_spin<R>[dag][flip][dir] = {lambda_k / 2, q_1..q_4} with q_mu = rho_k d_mu (negated for the adjoint)
+// and all five negated when flip = 1 (the fermion sign of a t-wrapping hop).  Wave-uniform, so the
+// row kernel reads them with scalar loads instead of recomputing them in every lane.
+constexpr int kSpinVals = 5;
+__constant__ float c_spin_f[2][2][81][kSpinVals];
+__constant__ double c_spin_d[2][2][81][kSpinVals];
+
+template <typename R>
+__device__ __forceinline__ const R* spin_table(int dag, int flip, int dir);
+template <>
+__device__ __forceinline__ const float* spin_table<float>(int dag, int flip, int dir) {
+    return c_spin_f[dag][flip][dir];
+}
+template <>
+__device__ __forceinline__ const double* spin_table<double>(int dag, int flip, int dir) {
+    return c_spin_d[dag][flip][dir];
+}
 
 // ---------------------------------------------------------------------------
 // Link construction: one thread per (stored direction, site); direction is the slow
@@ -346,8 +366,7 @@ __global__ __launch_bounds__(512) void brillouin_rows_kernel(const typename P::G
         if (rc < 26) fetch(rc + 1);
         if (active) {
             const int iy = rc % 3, iz = (rc / 3) % 3, it = rc / 9;
-            const int kt = it != 1, kyz = (iy != 1) + (iz != 1);
-            const R bsign = (g.apbc && ((it == 0 && ct == 0) || (it == 2 && ct == g.nt - 1))) ? R(-1) : R(1);
+            const int flip = (g.apbc && ((it == 0 && ct == 0) || (it == 2 && ct == g.nt - 1))) ? 1 : 0;
 #pragma unroll
             for (int ix = 0; ix < 3; ++ix) {
                 const int xn = wrap(x + ix - 1, g.nx);
@@ -367,24 +386,17 @@ __global__ __launch_bounds__(512) void brillouin_rows_kernel(const typename P::G
                 }
                 // W_d(n): stored at the own site (rc < 13, or rc = 13 with d_x = -1), else the
                 // adjoint of the stored link at n + d
+                // l holds the stored matrix; for the adjoint directions W_d(n) = l^+, applied below
+                // with conjugating multiply-adds instead of an explicit conjugate
                 cx<R> l[NC][NC];
                 const bool adj = rc > 13 || (rc == 13 && ix == 2);
                 const G* lp = lwin + (adj ? xn : x) * LW + (rc < 13 ? ix : (rc == 13 ? 2 : 2 - ix)) * L;
-                if (!adj) {
 #pragma unroll
-                    for (int a = 0; a < NC; ++a)
+                for (int a = 0; a < NC; ++a)
 #pragma unroll
-                        for (int b = 0; b < NC; ++b) l[a][b] = io<R, G>::ld(lp + a * NC + b);
-                } else {
-#pragma unroll
-                    for (int a = 0; a < NC; ++a)
-#pragma unroll
-                        for (int b = 0; b < NC; ++b) l[b][a] = cconj(io<R, G>::ld(lp + a * NC + b));
-                }
-                const int kh = kt + kyz + (ix != 1);
-                const R rhok = bsign * static_cast<R>(DAG ? -c_rho[kh] : c_rho[kh]);
-                const R lh = bsign * static_cast<R>(c_halflam[kh]);
-                const R q1 = rhok * (ix - 1), q2 = rhok * (iy - 1), q3 = rhok * (iz - 1), q4 = rhok * (it - 1);
+                    for (int b = 0; b < NC; ++b) l[a][b] = io<R, G>::ld(lp + a * NC + b);
+                const R* sv = spin_table<R>(DAG ? 1 : 0, flip, 27 * it + 9 * iz + 3 * iy + ix);
+                const R lh = sv[0], q1 = sv[1], q2 = sv[2], q3 = sv[3], q4 = sv[4];
 #pragma unroll
                 for (int k = 0; k < RB; ++k) {
                     cx<R> p[NC][4];
@@ -395,10 +407,17 @@ __global__ __launch_bounds__(512) void brillouin_rows_kernel(const typename P::G
 #pragma unroll
                     for (int a = 0; a < NC; ++a) {
                         cx<R> ch[4] = {{R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}};
+                        if (adj) {  // (l^+)[a][b] = conj(l[b][a])
 #pragma unroll
-                        for (int b = 0; b < NC; ++b)
+                            for (int b = 0; b < NC; ++b)
 #pragma unroll
-                            for (int s = 0; s < 4; ++s) cfma(ch[s], l[a][b], p[b][s]);
+                                for (int s = 0; s < 4; ++s) cfma_conj(ch[s], l[b][a], p[b][s]);
+                        } else {
+#pragma unroll
+                            for (int b = 0; b < NC; ++b)
+#pragma unroll
+                                for (int s = 0; s < 4; ++s) cfma(ch[s], l[a][b], p[b][s]);
+                        }
                         spin_accumulate(acc[k][a], ch, lh, q1, q2, q3, q4, ix != 1, iy != 1, iz != 1, it != 1);
                     }
                 }
@@ -421,6 +440,36 @@ __global__ __launch_bounds__(512) void brillouin_rows_kernel(const typename P::G
     for (uint32_t u = tid; u < total; u += blockDim.x) dst[u] = rtile[u + fast_div(u, rt.magic_units)];
 }
 
+
+// Fill c_spin_f / c_spin_d on the current device (once per device, thread-safe).  false on failure.
+bool ensure_spin_table() {
+    static std::mutex mu;
+    static bool done[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
+    std::lock_guard<std::mutex> lock(mu);
+    if (done[dev]) return true;
+    const double rho[5] = {0.0, 64.0 / 432.0, 16.0 / 432.0, 4.0 / 432.0, 1.0 / 432.0};
+    const double halflam[5] = {-120.0 / 64.0, 4.0 / 64.0, 2.0 / 64.0, 1.0 / 64.0, 0.5 / 64.0};
+    static double td[2][2][81][kSpinVals];
+    static float tf[2][2][81][kSpinVals];
+    for (int dag = 0; dag < 2; ++dag)
+        for (int flip = 0; flip < 2; ++flip)
+            for (int dir = 0; dir < 81; ++dir) {
+                const int d[4] = {dir % 3 - 1, (dir / 3) % 3 - 1, (dir / 9) % 3 - 1, dir / 27 - 1};
+                const int k = (d[0] != 0) + (d[1] != 0) + (d[2] != 0) + (d[3] != 0);
+                const double sg = flip ? -1.0 : 1.0;
+                const double r = sg * (dag ? -rho[k] : rho[k]);
+                td[dag][flip][dir][0] = sg * halflam[k];
+                for (int mu = 0; mu < 4; ++mu) td[dag][flip][dir][1 + mu] = r * d[mu];
+                for (int v = 0; v < kSpinVals; ++v) tf[dag][flip][dir][v] = static_cast<float>(td[dag][flip][dir][v]);
+            }
+    if (hipMemcpyToSymbol(HIP_SYMBOL(c_spin_d), td, sizeof(td)) != hipSuccess) return false;
+    if (hipMemcpyToSymbol(HIP_SYMBOL(c_spin_f), tf, sizeof(tf)) != hipSuccess) return false;
+    done[dev] = true;
+    return true;
+}
+
 template <int NC, int RB, class P>
 bool launch_rows(const StencilArgs& a, hipStream_t st) {
     using S = typename P::S;
@@ -430,6 +479,7 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
     const int nrg = a.nv / RB;
     const int64_t rows = a.g.vol / a.g.nx;
     if (choose_tile_rows(a.variant, rows, a.g.nx, units, nrg) != 1) return false;
+    if (!ensure_spin_table()) return false;  // the direct kernel needs no table
     if (row_tile_lds(a.g.nx, units) > 64 * 1024) return false;
     // the link window (3 links per site) is staged with at most 4 elements per thread
     if (static_cast<int64_t>(a.g.nx) * 3 * NC * NC > 4 * static_cast<int64_t>(a.g.nx) * nrg) return false;
