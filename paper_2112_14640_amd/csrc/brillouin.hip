@@ -273,8 +273,8 @@ __global__ __launch_bounds__(256) void brillouin_kernel(const typename P::G* __r
 // are the links of the directions 80 - dir (Tab. off-axis); for rc = 13 direction 39 of the own
 // row serves d_x = -1 as stored and d_x = +1 as the adjoint at x + 1.  The next row copy is in
 // flight (in registers) while the current one is consumed.
-template <int NC, int RB, bool DAG, class P, int NVC>
-__global__ __launch_bounds__(512) void brillouin_rows_kernel(const typename P::G* __restrict__ W,
+template <int NC, int RB, bool DAG, class P, int NVC, bool SEG>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void brillouin_rows_kernel(const typename P::G* __restrict__ W,
                                                              const typename P::S* __restrict__ in,
                                                              typename P::S* __restrict__ out, typename P::R diag,
                                                              Geom g, int nv, RowTile rt) {
@@ -289,13 +289,16 @@ __global__ __launch_bounds__(512) void brillouin_rows_kernel(const typename P::G
 
     const int64_t tix = logical_block();
     if (tix >= rt.ntiles) return;
-    const uint32_t rho = tile_row(static_cast<uint32_t>(tix), rt, g);
+    const uint32_t nseg = static_cast<uint32_t>(rt.nseg);
+    const uint32_t rq = static_cast<uint32_t>(tix) / nseg;
+    const int x0 = static_cast<int>(static_cast<uint32_t>(tix) - rq * nseg) * rt.S;  // first site of the segment
+    const uint32_t rho = tile_row(rq, rt, g);
     const uint32_t tid = threadIdx.x;
     const bool active = tid < static_cast<uint32_t>(rt.threads);
     const uint32_t tt = active ? tid : tid - rt.threads;  // padding threads shadow a real one
-    const uint32_t j = fast_div(tt, rt.magic_nrg);
+    const uint32_t j = fast_div(tt, rt.magic_nrg);      // site within the segment
     const int rg = static_cast<int>(tt - j * rt.nrg);
-    const int x = static_cast<int>(j);
+    const int x = x0 + static_cast<int>(j);
     int cy, cz, ct;
     {
         const uint32_t q = rho / static_cast<uint32_t>(g.ny);
@@ -306,14 +309,32 @@ __global__ __launch_bounds__(512) void brillouin_rows_kernel(const typename P::G
     }
     const int64_t own_start = static_cast<int64_t>(rho) * g.nx;
     const u32x4* src = reinterpret_cast<const u32x4*>(in);
-    G* lwin = reinterpret_cast<G*>(rtile + rt.S * (rt.units + 1));  // S * LW link elements
-    const uint32_t nlink = static_cast<uint32_t>(rt.S) * LW;
-    constexpr int PERL = 4;  // link elements per thread (threads >= 64 * ... checked at launch)
-    uint32_t slot[PER];
+    // LDS: with SEG, copy site c = 0 .. S + 1 holds x = x0 - 1 + c (periodic); without, the whole row
+    // (c = x, S = n_x, neighbours wrap inside it).  Then the link window.
+    constexpr int OFF = SEG ? 1 : 0;  // copy site of the segment's first site
+    const int SC = rt.S + 2 * OFF;    // sites per copy
+    G* lwin = reinterpret_cast<G*>(rtile + SC * (rt.units + 1));  // SC * LW link elements
+    const uint32_t nlink = static_cast<uint32_t>(SC) * LW;
+    constexpr int PERL = 4;  // link elements per thread (checked at launch)
+    uint32_t slot[PER];      // main units: the S sites of the segment, copy sites 1 .. S
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const uint32_t u = k * static_cast<uint32_t>(rt.threads) + tt;
-        slot[k] = u + fast_div(u, rt.magic_units);
+        slot[k] = u + fast_div(u, rt.magic_units) + OFF * (rt.units + 1);
+    }
+    // halo units h = tt and tt + threads (< 2 units) copy the sites x0 - 1 (copy site 0) and x0 + S
+    // (copy site S + 1)
+    bool halo[2];
+    uint32_t hslot[2];
+    uint32_t hsrc[2];  // unit index relative to the start of the copied row
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const uint32_t h = tt + q * static_cast<uint32_t>(rt.threads);
+        halo[q] = SEG && h < 2u * rt.units;
+        const uint32_t hs = h < static_cast<uint32_t>(rt.units) ? 0u : 1u;
+        const uint32_t hcu = h - hs * rt.units;
+        hslot[q] = (hs ? rt.S + 1 : 0) * (rt.units + 1) + hcu;
+        hsrc[q] = static_cast<uint32_t>(hs ? wrap(x0 + rt.S, g.nx) : wrap(x0 - 1, g.nx)) * rt.units + hcu;
     }
     auto row_start = [&](int rc) __attribute__((always_inline)) {
         const int dy = rc % 3 - 1, dz = (rc / 3) % 3 - 1, dt = rc / 9 - 1;
@@ -321,14 +342,18 @@ __global__ __launch_bounds__(512) void brillouin_rows_kernel(const typename P::G
         return ((static_cast<int64_t>(t) * g.nz + z) * g.ny + y) * g.nx;
     };
     u32x4 pre[PER];
+    u32x4 hpre[2];
     G lpre[PERL];
     auto fetch = [&](int rc) __attribute__((always_inline)) {
         const int64_t start = row_start(rc);
-        const u32x4* p = src + start * rt.units + tt;
+        const u32x4* p = src + (start + x0) * rt.units + tt;
 #pragma unroll
         for (int k = 0; k < PER; ++k) pre[k] = p[static_cast<int64_t>(k) * rt.threads];
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            if (SEG && halo[q]) hpre[q] = src[start * rt.units + hsrc[q]];
         const int dir0 = 9 * (3 * (rc / 9) + (rc / 3) % 3) + 3 * (rc % 3);
-        const int64_t lstart = rc < 13 ? own_start : (rc == 13 ? own_start : start);
+        const int64_t lstart = rc <= 13 ? own_start : start;
         const int wb = rc < 13 ? dir0 : (rc == 13 ? 37 : 78 - dir0);
 #pragma unroll
         for (int k = 0; k < PERL; ++k) {
@@ -336,12 +361,13 @@ __global__ __launch_bounds__(512) void brillouin_rows_kernel(const typename P::G
             if (u < nlink) {
                 const uint32_t sx = u / LW;
                 const uint32_t e = u - sx * LW;
-                lpre[k] = W[((lstart + sx) * 40 + wb) * L + e];
+                const int xs = SEG ? wrap(x0 - 1 + static_cast<int>(sx), g.nx) : static_cast<int>(sx);
+                lpre[k] = W[((lstart + xs) * 40 + wb) * L + e];
             }
         }
     };
-    auto at = [&](int xx) __attribute__((always_inline)) {
-        return reinterpret_cast<const S*>(rtile + xx * (rt.units + 1)) + rg * RB;
+    auto at = [&](int c) __attribute__((always_inline)) {
+        return reinterpret_cast<const S*>(rtile + c * (rt.units + 1)) + rg * RB;
     };
 
     cx<R> acc[RB][NC][4];
@@ -358,6 +384,9 @@ __global__ __launch_bounds__(512) void brillouin_rows_kernel(const typename P::G
 #pragma unroll
         for (int k = 0; k < PER; ++k) rtile[slot[k]] = pre[k];
 #pragma unroll
+        for (int q = 0; q < 2; ++q)
+            if (SEG && halo[q]) rtile[hslot[q]] = hpre[q];
+#pragma unroll
         for (int k = 0; k < PERL; ++k) {
             const uint32_t u = k * static_cast<uint32_t>(rt.threads) + tt;
             if (u < nlink) lwin[u] = lpre[k];
@@ -369,8 +398,9 @@ __global__ __launch_bounds__(512) void brillouin_rows_kernel(const typename P::G
             const int flip = (g.apbc && ((it == 0 && ct == 0) || (it == 2 && ct == g.nt - 1))) ? 1 : 0;
 #pragma unroll
             for (int ix = 0; ix < 3; ++ix) {
-                const int xn = wrap(x + ix - 1, g.nx);
-                const S* nbp = at(xn);
+                // copy site of x + ix - 1
+                const int cn = SEG ? static_cast<int>(j) + ix : wrap(static_cast<int>(j) + ix - 1, g.nx);
+                const S* nbp = at(cn);
                 if (rc == 13 && ix == 1) {  // the centre: (m - lambda_0 / 2) u(n)
 #pragma unroll
                     for (int k = 0; k < RB; ++k)
@@ -390,7 +420,8 @@ __global__ __launch_bounds__(512) void brillouin_rows_kernel(const typename P::G
                 // with conjugating multiply-adds instead of an explicit conjugate
                 cx<R> l[NC][NC];
                 const bool adj = rc > 13 || (rc == 13 && ix == 2);
-                const G* lp = lwin + (adj ? xn : x) * LW + (rc < 13 ? ix : (rc == 13 ? 2 : 2 - ix)) * L;
+                const G* lp = lwin + (adj ? cn : static_cast<int>(j) + OFF) * LW +
+                              (rc < 13 ? ix : (rc == 13 ? 2 : 2 - ix)) * L;
 #pragma unroll
                 for (int a = 0; a < NC; ++a)
 #pragma unroll
@@ -426,7 +457,7 @@ __global__ __launch_bounds__(512) void brillouin_rows_kernel(const typename P::G
     }
     __syncthreads();
     if (active) {
-        S* o = const_cast<S*>(at(x));
+        S* o = const_cast<S*>(at(static_cast<int>(j) + OFF));
 #pragma unroll
         for (int k = 0; k < RB; ++k)
 #pragma unroll
@@ -435,9 +466,9 @@ __global__ __launch_bounds__(512) void brillouin_rows_kernel(const typename P::G
                 for (int s = 0; s < 4; ++s) io<R, S>::st(o + (a * 4 + s) * nv + k, acc[k][a][s]);
     }
     __syncthreads();
-    u32x4* dst = reinterpret_cast<u32x4*>(out) + own_start * rt.units;
+    u32x4* dst = reinterpret_cast<u32x4*>(out) + (own_start + x0) * rt.units;
     const uint32_t total = static_cast<uint32_t>(rt.S) * rt.units;
-    for (uint32_t u = tid; u < total; u += blockDim.x) dst[u] = rtile[u + fast_div(u, rt.magic_units)];
+    for (uint32_t u = tid; u < total; u += blockDim.x) dst[u] = rtile[u + fast_div(u, rt.magic_units) + OFF * (rt.units + 1)];
 }
 
 
@@ -478,27 +509,41 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
     const int units = static_cast<int>(block_bytes / 16);
     const int nrg = a.nv / RB;
     const int64_t rows = a.g.vol / a.g.nx;
-    if (choose_tile_rows(a.variant, rows, a.g.nx, units, nrg) != 1) return false;
+    // segment: the largest divisor of n_x with at most 256 threads (at most 512 if none), at least
+    // 64 threads and enough threads for the two halo sites (two units each) and the link window
+    auto fits = [&](int d, int cap) {
+        const int64_t th = static_cast<int64_t>(d) * nrg;
+        return a.g.nx % d == 0 && th <= cap && th >= 64 && units <= th &&
+               static_cast<int64_t>(d + 2) * 3 * NC * NC <= 4 * th;
+    };
+    int seg = 0;
+    for (int cap : {256, 512}) {
+        for (int d = a.g.nx; d >= 1 && !seg; --d)
+            if (fits(d, cap)) seg = d;
+        if (seg) break;
+    }
+    if (seg == 0) return false;
+    const bool segmented = seg != a.g.nx;
+    const int sc = seg + (segmented ? 2 : 0);  // sites per copy
+    const size_t lds = static_cast<size_t>(sc) * (units + 1) * 16 +
+                       static_cast<size_t>(sc) * 3 * NC * NC * sizeof(typename P::G);
+    if (lds > 64 * 1024) return false;
     if (!ensure_spin_table()) return false;  // the direct kernel needs no table
-    if (row_tile_lds(a.g.nx, units) > 64 * 1024) return false;
-    // the link window (3 links per site) is staged with at most 4 elements per thread
-    if (static_cast<int64_t>(a.g.nx) * 3 * NC * NC > 4 * static_cast<int64_t>(a.g.nx) * nrg) return false;
     RowTile rt{};
     rt.R = 1;
-    rt.S = a.g.nx;
+    rt.S = seg;
+    rt.nseg = a.g.nx / seg;
     rt.nrg = nrg;
     rt.units = units;
     rt.row_units = a.g.nx * units;
-    rt.threads = rt.S * nrg;
-    rt.ntiles = rows;
+    rt.threads = seg * nrg;
+    rt.ntiles = rows * rt.nseg;
     rt.magic_nrg = div_magic(nrg);
     rt.magic_nx = div_magic(a.g.nx);
     rt.magic_units = div_magic(units);
     rt.magic_row_units = div_magic(rt.row_units);
     row_order(4, a.g, rt);
     const int block = (rt.threads + 63) / 64 * 64;
-    const size_t lds = row_tile_lds(rt.S, units) + static_cast<size_t>(rt.S) * 3 * NC * NC * sizeof(typename P::G);
-    if (lds > 64 * 1024) return false;
     const dim3 grid(static_cast<unsigned>(grid_blocks_x8(rt.ntiles, 1)));
     using R = typename P::R;
     const R diag = static_cast<R>(a.mass + 120.0 / 64.0);
@@ -506,17 +551,24 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
     auto in = static_cast<const S*>(a.in);
     auto out = static_cast<S*>(a.out);
     auto go = [&](auto kern) { hipLaunchKernelGGL(kern, grid, dim3(block), lds, st, W, in, out, diag, a.g, a.nv, rt); };
-    if (a.nv == 12 && RB == 1) {
-        if (a.dagger)
-            go(brillouin_rows_kernel<NC, RB, true, P, 12>);
-        else
-            go(brillouin_rows_kernel<NC, RB, false, P, 12>);
-    } else {
-        if (a.dagger)
-            go(brillouin_rows_kernel<NC, RB, true, P, 0>);
-        else
-            go(brillouin_rows_kernel<NC, RB, false, P, 0>);
-    }
+    auto pick = [&](auto seg_c) {
+        constexpr bool SG = decltype(seg_c)::value;
+        if (a.nv == 12 && RB == 1) {
+            if (a.dagger)
+                go(brillouin_rows_kernel<NC, RB, true, P, 12, SG>);
+            else
+                go(brillouin_rows_kernel<NC, RB, false, P, 12, SG>);
+        } else {
+            if (a.dagger)
+                go(brillouin_rows_kernel<NC, RB, true, P, 0, SG>);
+            else
+                go(brillouin_rows_kernel<NC, RB, false, P, 0, SG>);
+        }
+    };
+    if (segmented)
+        pick(std::true_type{});
+    else
+        pick(std::false_type{});
     return true;
 }
 

@@ -133,7 +133,8 @@ struct RowTile {
     int units;             // 16-byte units per site block
     int row_units;         // nx * units
     int threads;           // S * nrg active threads
-    int64_t ntiles;        // rows / R
+    int64_t ntiles;        // rows / R (times nseg)
+    int nseg;              // x-segments per row (Brillouin; 1 for the others)
     uint32_t magic_nrg, magic_nx, magic_units, magic_row_units;
     // Tile order.  The t range is cut into slabs of ts slices, one slab per XCD when nt allows
     // (the launch gives each XCD a contiguous eighth of the tiles), so only the +-t copies at a

@@ -233,13 +233,16 @@ def test_wilson_row_tiles(case, prec, variant):
 
 
 BRILLOUIN_ROW_CASES = [
-    # dims, nc, nv, antiperiodic: rows of 6, 8 and 7 sites (at least 64 threads per row); the last
-    # case does not fit a row tile (a site block of 56 bytes) and takes the direct kernel
+    # dims, nc, nv, antiperiodic: rows of 6, 8 and 7 sites (at least 64 threads per row); the fifth
+    # case does not fit a row tile (a site block of 56 bytes) and takes the direct kernel; the last
+    # two cut rows of 32 and 48 sites into x-segments with one halo site on each side
     ((6, 4, 4, 6), 3, 12, True),
     ((8, 2, 6, 4), 2, 8, False),
     ((7, 2, 2, 4), 3, 12, True),
     ((6, 2, 2, 4), 4, 12, True),
     ((4, 4, 2, 2), 1, 7, True),
+    ((32, 2, 2, 4), 3, 12, True),  # rows cut into segments of 16 sites (FP32, FP64) or 32 (BF16)
+    ((48, 2, 2, 2), 3, 12, True),
 ]
 
 
