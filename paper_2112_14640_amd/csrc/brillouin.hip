@@ -542,7 +542,7 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
     rt.magic_nx = div_magic(a.g.nx);
     rt.magic_units = div_magic(units);
     rt.magic_row_units = div_magic(rt.row_units);
-    row_order(4, a.g, rt);
+    if (!row_order(4, a.g, rt)) return false;
     const int block = (rt.threads + 63) / 64 * 64;
     const dim3 grid(static_cast<unsigned>(grid_blocks_x8(rt.ntiles, 1)));
     using R = typename P::R;

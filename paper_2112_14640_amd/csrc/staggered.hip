@@ -262,7 +262,8 @@ __global__ __launch_bounds__(512) void staggered_rows_kernel(const typename P::G
 
     const int64_t tix = logical_block();
     if (tix >= rt.ntiles) return;
-    const uint32_t rho = tile_row(static_cast<uint32_t>(tix), rt, g);
+    const RowPos pos = tile_row_pos(static_cast<uint32_t>(tix), rt, g);
+    const uint32_t rho = row_index(pos, g);
     const uint32_t tid = threadIdx.x;
     const bool active = tid < static_cast<uint32_t>(rt.threads);
     const uint32_t tt = active ? tid : tid - rt.threads;
@@ -271,14 +272,7 @@ __global__ __launch_bounds__(512) void staggered_rows_kernel(const typename P::G
     const int x = static_cast<int>(j);
     const int64_t rowsite = static_cast<int64_t>(rho) * g.nx;
     const int64_t site = rowsite + x;
-    int cy, cz, ct;
-    {
-        const uint32_t q = rho / static_cast<uint32_t>(g.ny);
-        cy = static_cast<int>(rho - q * g.ny);
-        const uint32_t q2 = q / static_cast<uint32_t>(g.nz);
-        cz = static_cast<int>(q - q2 * g.nz);
-        ct = static_cast<int>(q2);
-    }
+    const int cy = pos.y, cz = pos.z, ct = pos.t;
     const Unit* src = reinterpret_cast<const Unit*>(in);
     uint32_t slot[PER];
 #pragma unroll
@@ -287,10 +281,13 @@ __global__ __launch_bounds__(512) void staggered_rows_kernel(const typename P::G
         slot[k] = u + fast_div(u, rt.magic_units);
     }
     Unit pre[PER];
+    const uint32_t row_bytes = static_cast<uint32_t>(rt.row_units * sizeof(Unit));
     auto fetch = [&](int64_t row_start) __attribute__((always_inline)) {
-        const Unit* p = src + row_start * rt.units + tt;
+        const auto r = raw_buffer(src + row_start * rt.units, row_bytes);
 #pragma unroll
-        for (int k = 0; k < PER; ++k) pre[k] = p[static_cast<int64_t>(k) * rt.threads];
+        for (int k = 0; k < PER; ++k)
+            pre[k] = buffer_load_unit<Unit>(r, tt * static_cast<uint32_t>(sizeof(Unit)),
+                                            static_cast<uint32_t>(k * rt.threads * sizeof(Unit)));
     };
     auto stash = [&]() __attribute__((always_inline)) {
 #pragma unroll
@@ -324,7 +321,7 @@ __global__ __launch_bounds__(512) void staggered_rows_kernel(const typename P::G
     load_link(lxm, U + ((rowsite + xm) * 4 + 0) * L, true);
     stash();
     __syncthreads();
-    fetch(row_neighbour_start(rho, 0, g));
+    fetch(row_neighbour_start(pos, 0, g));
     load_link(lnext, U + (site * 4 + 1) * L, false);
     auto hop_acc = [&](const cx<R> (&l)[NC][NC], const S* nb, R scale) __attribute__((always_inline)) {
 #pragma unroll
@@ -362,7 +359,7 @@ __global__ __launch_bounds__(512) void staggered_rows_kernel(const typename P::G
         if constexpr (DIR < 5) {
             constexpr int ND = DIR + 1;
             constexpr int NMU = ND / 2 + 1;
-            const int64_t nrow = row_neighbour_start(rho, ND, g);
+            const int64_t nrow = row_neighbour_start(pos, ND, g);
             fetch(nrow);
             if constexpr (ND % 2 == 0)
                 load_link(lnext, U + (site * 4 + NMU) * L, false);
@@ -392,7 +389,10 @@ __global__ __launch_bounds__(512) void staggered_rows_kernel(const typename P::G
     __syncthreads();
     Unit* dst = reinterpret_cast<Unit*>(out) + rowsite * rt.units;
     const uint32_t total = static_cast<uint32_t>(rt.S) * rt.units;
-    for (uint32_t u = tid; u < total; u += blockDim.x) dst[u] = rtile[u + fast_div(u, rt.magic_units)];
+    // streaming stores: the output is not read again by this launch, so its lines should not
+    // displace input rows that neighbouring work-groups still read from L2
+    for (uint32_t u = tid; u < total; u += blockDim.x)
+        __builtin_nontemporal_store(rtile[u + fast_div(u, rt.magic_units)], dst + u);
 }
 
 template <int NC, int RB, class P>
@@ -424,7 +424,7 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
         rt.magic_nx = div_magic(a.g.nx);
         rt.magic_units = div_magic(units);
         rt.magic_row_units = div_magic(rt.row_units);
-        row_order(4, a.g, rt);
+        if (!row_order(4, a.g, rt)) return false;
         const int block = (rt.threads + 63) / 64 * 64;
         const dim3 grid(static_cast<unsigned>(grid_blocks_x8(rt.ntiles, 1)));
         using R = typename P::R;

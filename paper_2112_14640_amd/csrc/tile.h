@@ -142,16 +142,23 @@ struct RowTile {
     // then t, then the rows of the block, so the rows a tile shares with its +-y, +-z and +-t
     // neighbours are fetched close together in time.
     int by, bz, nby, ts;
+    // ceil(2^32 / d) for d = by * bz, by, ts, nby (0 when d = 1), exact over the ranges of
+    // tile_row (row_order checks that); a slab division is done only when there are several slabs
+    uint32_t magic_bsz, magic_by, magic_ts, magic_nby;
 };
 
-// First site of the row one step from row rho: dir 0..5 = +y, -y, +z, -z, +t, -t (periodic).
-__device__ __forceinline__ int64_t row_neighbour_start(uint32_t rho, int dir, const Geom& g) {
-    const uint32_t ny = static_cast<uint32_t>(g.ny), nz = static_cast<uint32_t>(g.nz);
-    const uint32_t q = rho / ny;
-    int y = static_cast<int>(rho - q * ny);
-    const uint32_t tq = q / nz;
-    int z = static_cast<int>(q - tq * nz);
-    int t = static_cast<int>(tq);
+// Lattice coordinates of a row (x = 0).
+struct RowPos {
+    int y, z, t;
+};
+
+__device__ __forceinline__ uint32_t row_index(const RowPos& p, const Geom& g) {
+    return static_cast<uint32_t>(p.y + g.ny * (p.z + g.nz * p.t));
+}
+
+// First site of the row one step from row p: dir 0..5 = +y, -y, +z, -z, +t, -t (periodic).
+__device__ __forceinline__ int64_t row_neighbour_start(const RowPos& p, int dir, const Geom& g) {
+    int y = p.y, z = p.z, t = p.t;
     switch (dir) {
         case 0: y = y + 1 == g.ny ? 0 : y + 1; break;
         case 1: y = y == 0 ? g.ny - 1 : y - 1; break;
@@ -168,6 +175,22 @@ __device__ __forceinline__ int64_t row_neighbour_start(uint32_t rho, int dir, co
 using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
 using u32x2 = unsigned int __attribute__((ext_vector_type(2)));
 
+// Raw buffer resource over `bytes` bytes from `base` (gfx9 descriptor: 32-bit data format, no
+// stride).  Row copies load through it with a per-lane offset fixed for the kernel and a
+// work-group-uniform offset, so their address arithmetic stays on the scalar unit; a read at or
+// past `bytes` returns zero instead of touching memory.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_buffer(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, static_cast<int>(bytes), 0x00020000);
+}
+
+template <typename Unit>
+__device__ __forceinline__ Unit buffer_load_unit(__amdgpu_buffer_rsrc_t r, uint32_t lane_off, uint32_t uni_off) {
+    if constexpr (sizeof(Unit) == 16)
+        return __builtin_bit_cast(Unit, __builtin_amdgcn_raw_buffer_load_b128(r, lane_off, uni_off, 0));
+    else
+        return __builtin_bit_cast(Unit, __builtin_amdgcn_raw_buffer_load_b64(r, lane_off, uni_off, 0));
+}
+
 // 16-byte units each thread moves per row copy of a four-spin field: its share of the row.
 template <int NC, int RB, class P>
 struct RowUnits {
@@ -177,31 +200,41 @@ struct RowUnits {
 // Bytes of LDS for one staged row tile (site stride padded by one 16-byte unit).
 inline size_t row_tile_lds(int S, int units) { return static_cast<size_t>(S) * (units + 1) * 16; }
 
-// Row processed by tile number T (after the XCD remap) in the order of RowTile.
-__device__ __forceinline__ uint32_t tile_row(uint32_t T, const RowTile& rt, const Geom& g) {
-    const uint32_t plane = static_cast<uint32_t>(g.ny * g.nz);
-    const uint32_t slab_rows = plane * static_cast<uint32_t>(rt.ts);
-    const uint32_t slab = T / slab_rows;
-    const uint32_t T2 = T - slab * slab_rows;
+// Row processed by tile number T (after the XCD remap) in the order of RowTile.  The divisors
+// are uniform over the work-group; the magic multiplies keep them on the scalar unit.
+__device__ __forceinline__ RowPos tile_row_pos(uint32_t T, const RowTile& rt, const Geom& g) {
+    uint32_t slab = 0, T2 = T;
+    if (rt.ts != g.nt) {
+        const uint32_t slab_rows = static_cast<uint32_t>(g.ny * g.nz) * static_cast<uint32_t>(rt.ts);
+        slab = T / slab_rows;
+        T2 = T - slab * slab_rows;
+    }
     const uint32_t bsz = static_cast<uint32_t>(rt.by * rt.bz);
-    const uint32_t q = T2 / bsz;
+    const uint32_t q = fast_div(T2, rt.magic_bsz);
     const uint32_t rin = T2 - q * bsz;
-    const uint32_t b = q / static_cast<uint32_t>(rt.ts);
+    const uint32_t b = fast_div(q, rt.magic_ts);
     const uint32_t t = slab * rt.ts + (q - b * static_cast<uint32_t>(rt.ts));
-    const uint32_t bzi = b / static_cast<uint32_t>(rt.nby);
+    const uint32_t bzi = fast_div(b, rt.magic_nby);
     const uint32_t byi = b - bzi * static_cast<uint32_t>(rt.nby);
-    const uint32_t zin = rin / static_cast<uint32_t>(rt.by);
+    const uint32_t zin = fast_div(rin, rt.magic_by);
     const uint32_t y = byi * rt.by + (rin - zin * rt.by);
     const uint32_t z = bzi * rt.bz + zin;
-    return y + static_cast<uint32_t>(g.ny) * (z + static_cast<uint32_t>(g.nz) * t);
+    return {static_cast<int>(y), static_cast<int>(z), static_cast<int>(t)};
+}
+
+__device__ __forceinline__ uint32_t tile_row(uint32_t T, const RowTile& rt, const Geom& g) {
+    return row_index(tile_row_pos(T, rt, g), g);
 }
 
 // Block extent of the row order along one axis: `want` when it divides n, else 2, else 1.
 inline int row_block_extent(int n, int want) { return n % want == 0 ? want : (n % 2 == 0 ? 2 : 1); }
 
+inline bool row_order_magic(const Geom& g, RowTile& rt);
+
 // Row order of variants 4 and 5 (4 x 4 (y, z) blocks over the whole t range), 6 (lexicographic),
-// 7 (t slabs, one per XCD, 4 x 4 blocks inside).
-inline void row_order(int variant, const Geom& g, RowTile& rt) {
+// 7 (t slabs, one per XCD, 4 x 4 blocks inside).  False if its divisions cannot be done exactly
+// with 32-bit magic multiplies (the row kernels are then not used).
+inline bool row_order(int variant, const Geom& g, RowTile& rt) {
     if (variant == 6) {
         rt.by = g.ny;
         rt.bz = g.nz;
@@ -218,6 +251,24 @@ inline void row_order(int variant, const Geom& g, RowTile& rt) {
                 }
     }
     rt.nby = g.ny / rt.by;
+    return row_order_magic(g, rt);
+}
+
+// ceil(2^32 / d) when umulhi(u, magic) == u / d for every u < umax (0 for d = 1); false if not.
+inline bool exact_magic(uint32_t d, uint64_t umax, uint32_t& magic) {
+    magic = div_magic(d);
+    if (d <= 1) return true;
+    const uint64_t e = static_cast<uint64_t>(magic) * d - 0x100000000ull;
+    return umax * e < 0x100000000ull;
+}
+
+// Magic divisors of tile_row_pos for the order row_order chose; false if one is not exact.
+inline bool row_order_magic(const Geom& g, RowTile& rt) {
+    const uint64_t slab_rows = static_cast<uint64_t>(g.ny) * g.nz * rt.ts;
+    const uint32_t bsz = static_cast<uint32_t>(rt.by * rt.bz);
+    return exact_magic(bsz, slab_rows, rt.magic_bsz) && exact_magic(rt.by, bsz, rt.magic_by) &&
+           exact_magic(rt.ts, slab_rows / bsz, rt.magic_ts) &&
+           exact_magic(rt.nby, static_cast<uint64_t>(rt.nby) * (g.nz / rt.bz), rt.magic_nby);
 }
 
 // LDS a work-group may request on the current device (64 KiB unless the device reports more;

@@ -97,6 +97,36 @@ __device__ __forceinline__ void reconstruct_add(cx<R> acc[4], cx<R> c0, cx<R> c1
     }
 }
 
+// acc[0..3] += s * (full spinor rebuilt from c0, c1): the scale rides on the multiply-adds.
+template <int MU, int SIG, typename R>
+__device__ __forceinline__ void reconstruct_scaled(cx<R> acc[4], cx<R> c0, cx<R> c1, R s) {
+    // a += f v and a += f i v (i v = (-v.im, v.re)), f = +-s
+    auto ax = [](cx<R>& a, R f, cx<R> v) __attribute__((always_inline)) {
+        a.re += f * v.re;
+        a.im += f * v.im;
+    };
+    auto axi = [](cx<R>& a, R f, cx<R> v) __attribute__((always_inline)) {
+        a.re -= f * v.im;
+        a.im += f * v.re;
+    };
+    const R n = -s;
+    ax(acc[0], s, c0);
+    ax(acc[1], s, c1);
+    if constexpr (MU == 0) {  // r2 = SIG i c1, r3 = SIG i c0
+        axi(acc[2], SIG > 0 ? s : n, c1);
+        axi(acc[3], SIG > 0 ? s : n, c0);
+    } else if constexpr (MU == 1) {  // r2 = SIG c1, r3 = -SIG c0
+        ax(acc[2], SIG > 0 ? s : n, c1);
+        ax(acc[3], SIG > 0 ? n : s, c0);
+    } else if constexpr (MU == 2) {  // r2 = SIG i c0, r3 = -SIG i c1
+        axi(acc[2], SIG > 0 ? s : n, c0);
+        axi(acc[3], SIG > 0 ? n : s, c1);
+    } else {  // r2 = SIG c0, r3 = SIG c1
+        ax(acc[2], SIG > 0 ? s : n, c0);
+        ax(acc[3], SIG > 0 ? s : n, c1);
+    }
+}
+
 // L = link (ADJ = false) or link^+ (ADJ = true) into registers.
 template <int NC, bool ADJ, class P>
 __device__ __forceinline__ void load_link(cx<typename P::R> (&l)[NC][NC], const typename P::G* __restrict__ link) {
@@ -130,10 +160,6 @@ __device__ __forceinline__ void hop_with(cx<typename P::R> (&acc)[RB][NC][4], co
 #pragma unroll
             for (int s = 0; s < 4; ++s) p[s] = io<R, typename P::S>::ld(nb + (b * 4 + s) * stride + k);
             project<MU, SIG>(p, h0[b], h1[b]);
-            if constexpr (SCALED) {
-                h0[b] = cscale(scale, h0[b]);
-                h1[b] = cscale(scale, h1[b]);
-            }
         }
 #pragma unroll
         for (int a = 0; a < NC; ++a) {
@@ -143,7 +169,10 @@ __device__ __forceinline__ void hop_with(cx<typename P::R> (&acc)[RB][NC][4], co
                 cfma(c0, l[a][b], h0[b]);
                 cfma(c1, l[a][b], h1[b]);
             }
-            reconstruct_add<MU, SIG>(acc[k][a], c0, c1);
+            if constexpr (SCALED)
+                reconstruct_scaled<MU, SIG>(acc[k][a], c0, c1, scale);
+            else
+                reconstruct_add<MU, SIG>(acc[k][a], c0, c1);
         }
     }
 }
@@ -429,7 +458,7 @@ __global__ __launch_bounds__(512) void wilson_lds_kernel(const typename P::G* __
 // loads of one direction overlap the arithmetic of the previous one.  The output tile leaves
 // through LDS as one contiguous store.
 
-template <int NC, int RB, bool DAG, class P, int NVC, bool UNSCALED>
+template <int NC, int RB, bool DAG, class P, int NVC>
 __global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* __restrict__ U,
                                                           const typename P::S* __restrict__ in,
                                                           typename P::S* __restrict__ out, typename P::R diag,
@@ -442,7 +471,8 @@ __global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* _
 
     const int64_t tix = logical_block();
     if (tix >= rt.ntiles) return;
-    const uint32_t rho = tile_row(static_cast<uint32_t>(tix), rt, g);  // one row per work-group
+    const RowPos pos = tile_row_pos(static_cast<uint32_t>(tix), rt, g);  // one row per work-group
+    const uint32_t rho = row_index(pos, g);
     const uint32_t tid = threadIdx.x;
     const bool active = tid < static_cast<uint32_t>(rt.threads);
     // padding threads (block rounded up to whole wavefronts) shadow a real thread: same loads and
@@ -453,7 +483,7 @@ __global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* _
     const int x = static_cast<int>(j);
     const int64_t rowsite = static_cast<int64_t>(rho) * g.nx;
     const int64_t site = rowsite + x;
-    const int ct = static_cast<int>(rho / static_cast<uint32_t>(g.ny) / static_cast<uint32_t>(g.nz));
+    const int ct = pos.t;
     const u32x4* src = reinterpret_cast<const u32x4*>(in);
     if constexpr (NVC > 0) nv = NVC;
 
@@ -465,10 +495,12 @@ __global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* _
         slot[k] = u + fast_div(u, rt.magic_units);
     }
     u32x4 pre[PER];
+    const uint32_t row_bytes = static_cast<uint32_t>(rt.row_units) * 16u;
     auto fetch = [&](int64_t row_start) __attribute__((always_inline)) {
-        const u32x4* p = src + row_start * rt.units + tt;
+        const auto r = raw_buffer(src + row_start * rt.units, row_bytes);
 #pragma unroll
-        for (int k = 0; k < PER; ++k) pre[k] = p[static_cast<int64_t>(k) * rt.threads];
+        for (int k = 0; k < PER; ++k)
+            pre[k] = buffer_load_unit<u32x4>(r, tt * 16u, static_cast<uint32_t>(k * rt.threads) * 16u);
     };
     auto stash = [&]() __attribute__((always_inline)) {
 #pragma unroll
@@ -490,12 +522,10 @@ __global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* _
     load_link<NC, true, P>(lxm, U + ((rowsite + xm) * 4 + 0) * L);
     stash();
     __syncthreads();
-    fetch(row_neighbour_start(rho, 0, g));
+    fetch(row_neighbour_start(pos, 0, g));
     load_link<NC, false, P>(lnext, U + (site * 4 + 1) * L);
-    // UNSCALED: the hops are summed without the 1/2 (acc starts at -2 (4 + m) u and is multiplied
-    // by -1/2 at the end); otherwise each half spinor is scaled by -1/2 (or +1/2 across the t
-    // boundary) before the link multiply
-    const R c0 = UNSCALED ? R(-2) * diag : diag;
+    // each transported half spinor enters the sum with -1/2 (+1/2 across the antiperiodic t
+    // boundary) as the multiplier of the rebuild's multiply-adds
     if (active) {
         const S* mine = at(j);
 #pragma unroll
@@ -503,9 +533,9 @@ __global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* _
 #pragma unroll
             for (int a = 0; a < NC; ++a)
 #pragma unroll
-                for (int s = 0; s < 4; ++s) acc[k][a][s] = cscale(c0, io<R, S>::ld(mine + (a * 4 + s) * nv + k));
-        hop_with<NC, RB, 0, SF, P, !UNSCALED, NVC>(acc, lxp, at(xp), nv, R(-0.5));
-        hop_with<NC, RB, 0, -SF, P, !UNSCALED, NVC>(acc, lxm, at(xm), nv, R(-0.5));
+                for (int s = 0; s < 4; ++s) acc[k][a][s] = cscale(diag, io<R, S>::ld(mine + (a * 4 + s) * nv + k));
+        hop_with<NC, RB, 0, SF, P, true, NVC>(acc, lxp, at(xp), nv, R(-0.5));
+        hop_with<NC, RB, 0, -SF, P, true, NVC>(acc, lxm, at(xm), nv, R(-0.5));
     }
     auto step = [&](auto mu_c, auto back_c) __attribute__((always_inline)) {
         constexpr int MU = decltype(mu_c)::value;
@@ -522,7 +552,7 @@ __global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* _
         if constexpr (DIR < 5) {
             constexpr int ND = DIR + 1;
             constexpr int NMU = ND / 2 + 1;
-            const int64_t nrow = row_neighbour_start(rho, ND, g);
+            const int64_t nrow = row_neighbour_start(pos, ND, g);
             fetch(nrow);
             if constexpr (ND % 2 == 0) {
                 load_link<NC, false, P>(lnext, U + (site * 4 + NMU) * L);
@@ -532,15 +562,7 @@ __global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* _
         }
         if (active) {
             const bool wrap = MU == 3 && g.apbc && ct == (BACK ? 0 : g.nt - 1);  // fermion sign
-            if constexpr (UNSCALED) {
-                if (wrap) {
-#pragma unroll
-                    for (int a = 0; a < NC; ++a)
-#pragma unroll
-                        for (int b = 0; b < NC; ++b) lcur[a][b] = cscale(R(-1), lcur[a][b]);
-                }
-            }
-            hop_with<NC, RB, MU, (BACK ? -SF : SF), P, !UNSCALED, NVC>(acc, lcur, at(j), nv,
+            hop_with<NC, RB, MU, (BACK ? -SF : SF), P, true, NVC>(acc, lcur, at(j), nv,
                                                                         wrap ? R(0.5) : R(-0.5));
         }
     };
@@ -559,12 +581,15 @@ __global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* _
             for (int a = 0; a < NC; ++a)
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
-                    io<R, S>::st(o + (a * 4 + s) * nv + k, UNSCALED ? cscale(R(-0.5), acc[k][a][s]) : acc[k][a][s]);
+                    io<R, S>::st(o + (a * 4 + s) * nv + k, acc[k][a][s]);
     }
     __syncthreads();
     u32x4* dst = reinterpret_cast<u32x4*>(out) + rowsite * rt.units;
     const uint32_t total = static_cast<uint32_t>(rt.S) * rt.units;
-    for (uint32_t u = tid; u < total; u += blockDim.x) dst[u] = rtile[u + fast_div(u, rt.magic_units)];
+    // streaming stores: the output is not read again by this launch, so its lines should not
+    // displace input rows that neighbouring work-groups still read from L2
+    for (uint32_t u = tid; u < total; u += blockDim.x)
+        __builtin_nontemporal_store(rtile[u + fast_div(u, rt.magic_units)], dst + u);
 }
 
 template <int NC, int RB, class P>
@@ -589,7 +614,7 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
     rt.magic_nx = div_magic(a.g.nx);
     rt.magic_units = div_magic(units);
     rt.magic_row_units = div_magic(rt.row_units);
-    row_order(a.variant, a.g, rt);
+    if (!row_order(a.variant, a.g, rt)) return false;
     const int block = (rt.threads + 63) / 64 * 64;
     const size_t lds = row_tile_lds(rt.S, units);
     const dim3 grid(static_cast<unsigned>(grid_blocks_x8(rt.ntiles, 1)));
@@ -607,21 +632,16 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
         }
         hipLaunchKernelGGL(kern, grid, dim3(block), lds, st, U, in, out, diag, a.g, a.nv, rt);
     };
-    if (a.variant == 5) {  // per-hop scaling, runtime RHS stride
+    if (a.variant == 4 && a.nv == 12 && RB == 1) {  // the common multi-RHS count: constant offsets
         if (a.dagger)
-            go(wilson_rows_kernel<NC, RB, true, P, 0, false>);
+            go(wilson_rows_kernel<NC, RB, true, P, 12>);
         else
-            go(wilson_rows_kernel<NC, RB, false, P, 0, false>);
-    } else if (a.nv == 12 && RB == 1) {  // the common multi-RHS count: component offsets become constants
+            go(wilson_rows_kernel<NC, RB, false, P, 12>);
+    } else {  // runtime RHS stride
         if (a.dagger)
-            go(wilson_rows_kernel<NC, RB, true, P, 12, true>);
+            go(wilson_rows_kernel<NC, RB, true, P, 0>);
         else
-            go(wilson_rows_kernel<NC, RB, false, P, 12, true>);
-    } else {
-        if (a.dagger)
-            go(wilson_rows_kernel<NC, RB, true, P, 0, true>);
-        else
-            go(wilson_rows_kernel<NC, RB, false, P, 0, true>);
+            go(wilson_rows_kernel<NC, RB, false, P, 0>);
     }
     return ok;
 }
