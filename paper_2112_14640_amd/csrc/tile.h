@@ -226,19 +226,23 @@ __device__ __forceinline__ uint32_t tile_row(uint32_t T, const RowTile& rt, cons
     return row_index(tile_row_pos(T, rt, g), g);
 }
 
-// Block extent of the row order along one axis: `want` when it divides n, else 2, else 1.
-inline int row_block_extent(int n, int want) { return n % want == 0 ? want : (n % 2 == 0 ? 2 : 1); }
+// Block extent of the row order along one axis: `want` (a power of two) or the largest power of
+// two below it that divides n.
+inline int row_block_extent(int n, int want) {
+    while (want > 1 && n % want != 0) want /= 2;
+    return want;
+}
 
 inline bool row_order_magic(const Geom& g, RowTile& rt);
 
-// Row order of variants 4 and 5 (4 x 4 (y, z) blocks over the whole t range), 6 (lexicographic),
-// 7 (t slabs, one per XCD, 4 x 4 blocks inside).  False if its divisions cannot be done exactly
+// Row order of variants 4 and 5 (4 x 4 (y, z) blocks over the whole t range), 6 (8 x 8 blocks
+// over the whole t range), 7 (t slabs, one per XCD, 4 x 4 blocks inside).  False if its divisions cannot be done exactly
 // with 32-bit magic multiplies (the row kernels are then not used).
 inline bool row_order(int variant, const Geom& g, RowTile& rt) {
     if (variant == 6) {
-        rt.by = g.ny;
-        rt.bz = g.nz;
-        rt.ts = 1;
+        rt.by = row_block_extent(g.ny, 8);
+        rt.bz = row_block_extent(g.nz, 8);
+        rt.ts = g.nt;
     } else {
         rt.by = row_block_extent(g.ny, 4);
         rt.bz = row_block_extent(g.nz, 4);
