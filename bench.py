@@ -367,7 +367,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported (the multi-GPU "
-              "decomposition is a design, not part of this build)", file=sys.stderr)
+              "domain decomposition is designed but not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch

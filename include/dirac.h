@@ -186,7 +186,8 @@ typedef struct {
     int recompute_every;  /* 0: default (50 FP64, 20 lower) */
     double drift;         /* 0: default 0.01 */
     int mixed_scheme;     /* 0: reliable updates (default), 1: defect correction (restarted inner solves) */
-    double delta;         /* reliable update / inner reduction factor; 0: default (0.1) */
+    double delta;         /* reliable-update factor (0: default 0.1); with defect correction the inner
+                           * solves' relative tolerance (0: default 1e-5 FP32, 5e-2 BF16) */
     int max_outer;        /* defect-correction cycles; 0: default 100 */
 } dirac_solve_opts;
 

@@ -272,9 +272,11 @@ __global__ __launch_bounds__(256) void brillouin_kernel(const typename P::G* __r
 // own row; for rc > 13 the directions 78 - dir0 .. 80 - dir0 of the neighbour row, whose adjoints
 // are the links of the directions 80 - dir (Tab. off-axis); for rc = 13 direction 39 of the own
 // row serves d_x = -1 as stored and d_x = +1 as the adjoint at x + 1.  The next row copy is in
-// flight (in registers) while the current one is consumed.
+// flight (in registers) while the current one is consumed.  Three waves per SIMD cap the registers
+// at 168 (FP32 and BF16 fit, the segmented forms spill a few values); FP64, whose operands take
+// twice the registers, takes two waves per SIMD and up to 256.
 template <int NC, int RB, bool DAG, class P, int NVC, bool SEG>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void brillouin_rows_kernel(const typename P::G* __restrict__ W,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(typename P::R) == 8 ? 2 : 3))) void brillouin_rows_kernel(const typename P::G* __restrict__ W,
                                                              const typename P::S* __restrict__ in,
                                                              typename P::S* __restrict__ out, typename P::R diag,
                                                              Geom g, int nv, RowTile rt) {

@@ -57,46 +57,6 @@ __device__ __forceinline__ void project(const cx<R> p[4], cx<R>& h0, cx<R>& h1) 
     }
 }
 
-// acc[0..3] += full spinor rebuilt from the (already transported) half spinor c0, c1.
-template <int MU, int SIG, typename R>
-__device__ __forceinline__ void reconstruct_add(cx<R> acc[4], cx<R> c0, cx<R> c1) {
-    acc[0] = cadd(acc[0], c0);
-    acc[1] = cadd(acc[1], c1);
-    if constexpr (MU == 0) {  // r2 = SIG i c1, r3 = SIG i c0
-        if constexpr (SIG > 0) {
-            acc[2] = cadd(acc[2], cmuli(c1));
-            acc[3] = cadd(acc[3], cmuli(c0));
-        } else {
-            acc[2] = csub(acc[2], cmuli(c1));
-            acc[3] = csub(acc[3], cmuli(c0));
-        }
-    } else if constexpr (MU == 1) {  // r2 = SIG c1, r3 = -SIG c0
-        if constexpr (SIG > 0) {
-            acc[2] = cadd(acc[2], c1);
-            acc[3] = csub(acc[3], c0);
-        } else {
-            acc[2] = csub(acc[2], c1);
-            acc[3] = cadd(acc[3], c0);
-        }
-    } else if constexpr (MU == 2) {  // r2 = SIG i c0, r3 = -SIG i c1
-        if constexpr (SIG > 0) {
-            acc[2] = cadd(acc[2], cmuli(c0));
-            acc[3] = csub(acc[3], cmuli(c1));
-        } else {
-            acc[2] = csub(acc[2], cmuli(c0));
-            acc[3] = cadd(acc[3], cmuli(c1));
-        }
-    } else {  // r2 = SIG c0, r3 = SIG c1
-        if constexpr (SIG > 0) {
-            acc[2] = cadd(acc[2], c0);
-            acc[3] = cadd(acc[3], c1);
-        } else {
-            acc[2] = csub(acc[2], c0);
-            acc[3] = csub(acc[3], c1);
-        }
-    }
-}
-
 // acc[0..3] += s * (full spinor rebuilt from c0, c1): the scale rides on the multiply-adds.
 template <int MU, int SIG, typename R>
 __device__ __forceinline__ void reconstruct_scaled(cx<R> acc[4], cx<R> c0, cx<R> c1, R s) {
@@ -144,9 +104,9 @@ __device__ __forceinline__ void load_link(cx<typename P::R> (&l)[NC][NC], const 
         }
 }
 
-// acc += scale * (1 + SIG g_MU) L u_nb for a link matrix L already in registers.  SCALED = false
-// skips the scale (taken as 1); NVC > 0 fixes the RHS stride at compile time (else nv).
-template <int NC, int RB, int MU, int SIG, class P, bool SCALED = true, int NVC = 0>
+// acc += scale * (1 + SIG g_MU) L u_nb for a link matrix L already in registers.  NVC > 0 fixes
+// the RHS stride at compile time (else nv).
+template <int NC, int RB, int MU, int SIG, class P, int NVC = 0>
 __device__ __forceinline__ void hop_with(cx<typename P::R> (&acc)[RB][NC][4], const cx<typename P::R> (&l)[NC][NC],
                                          const typename P::S* __restrict__ nb, int nv, typename P::R scale) {
     using R = typename P::R;
@@ -169,10 +129,7 @@ __device__ __forceinline__ void hop_with(cx<typename P::R> (&acc)[RB][NC][4], co
                 cfma(c0, l[a][b], h0[b]);
                 cfma(c1, l[a][b], h1[b]);
             }
-            if constexpr (SCALED)
-                reconstruct_scaled<MU, SIG>(acc[k][a], c0, c1, scale);
-            else
-                reconstruct_add<MU, SIG>(acc[k][a], c0, c1);
+            reconstruct_scaled<MU, SIG>(acc[k][a], c0, c1, scale);
         }
     }
 }
@@ -534,8 +491,8 @@ __global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* _
             for (int a = 0; a < NC; ++a)
 #pragma unroll
                 for (int s = 0; s < 4; ++s) acc[k][a][s] = cscale(diag, io<R, S>::ld(mine + (a * 4 + s) * nv + k));
-        hop_with<NC, RB, 0, SF, P, true, NVC>(acc, lxp, at(xp), nv, R(-0.5));
-        hop_with<NC, RB, 0, -SF, P, true, NVC>(acc, lxm, at(xm), nv, R(-0.5));
+        hop_with<NC, RB, 0, SF, P, NVC>(acc, lxp, at(xp), nv, R(-0.5));
+        hop_with<NC, RB, 0, -SF, P, NVC>(acc, lxm, at(xm), nv, R(-0.5));
     }
     auto step = [&](auto mu_c, auto back_c) __attribute__((always_inline)) {
         constexpr int MU = decltype(mu_c)::value;
@@ -562,7 +519,7 @@ __global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* _
         }
         if (active) {
             const bool wrap = MU == 3 && g.apbc && ct == (BACK ? 0 : g.nt - 1);  // fermion sign
-            hop_with<NC, RB, MU, (BACK ? -SF : SF), P, true, NVC>(acc, lcur, at(j), nv,
+            hop_with<NC, RB, MU, (BACK ? -SF : SF), P, NVC>(acc, lcur, at(j), nv,
                                                                         wrap ? R(0.5) : R(-0.5));
         }
     };
