@@ -209,6 +209,10 @@ ROW_CASES = [
     ((3, 2, 2, 4), 3, 6, True),
     ((10, 2, 2, 2), 1, 2, True),
     ((4, 4, 2, 6), 4, 1, True),
+    # tile orders with 3 x 1 and 3 x 3 (y, z) block grids (ny = 12 in blocks of 4, nz = 6 in blocks of
+    # 2), blocks of one row (ny = 3, nz = 5) and t extents of 10 and 6 (the scalar magic divisions)
+    ((8, 12, 6, 10), 3, 12, True),
+    ((8, 3, 5, 6), 3, 8, False),
 ]
 
 
@@ -243,6 +247,7 @@ BRILLOUIN_ROW_CASES = [
     ((4, 4, 2, 2), 1, 7, True),
     ((32, 2, 2, 4), 3, 12, True),  # rows cut into segments of 16 sites (FP32, FP64) or 32 (BF16)
     ((48, 2, 2, 2), 3, 12, True),
+    ((6, 6, 3, 4), 3, 12, True),  # a 3 x 3 grid of 2 x 1 (y, z) blocks in the tile order
 ]
 
 
@@ -268,6 +273,7 @@ STAGGERED_ROW_CASES = [
     ((16, 2, 2, 4), 3, 12, True),
     ((8, 2, 2, 4), 2, 8, False),
     ((8, 2, 2, 2), 4, 12, True),
+    ((16, 6, 10, 6), 3, 12, True),  # 3 x 5 grid of 2 x 2 (y, z) blocks
 ]
 
 
