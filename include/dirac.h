@@ -211,7 +211,9 @@ int bicgstab_solve(dirac_op op, dirac_prec outer, dirac_prec inner, const void* 
  * loads, the next hop direction in flight while the current one is consumed; rows taken in
  * 4 x 4 (y, z) blocks with t next; the RHS stride is a compile-time constant when nv = 12),
  * 5 the same with a runtime RHS stride, 6 the same in 8 x 8 (y, z) blocks, 7 t slabs (one per XCD) of
- * 4 x 4 blocks.  Brillouin: 4 row tiles (a work-group walks
+ * 4 x 4 blocks, 8 as 4 with each direction's links staged in LDS beside the row copy (nv = 12,
+ * 1 RHS per thread; otherwise as 5).  Variant 8 is Wilson only (the other operators run it as
+ * direct loads).  Brillouin: 4 row tiles (a work-group walks
  * the 27 neighbouring x-rows of its row, each staged in LDS with a window of three links per
  * site), anything else direct global loads.  Staggered: 4 row tiles as for Wilson (one x-row
  * per work-group, the six other neighbour rows staged in turn).

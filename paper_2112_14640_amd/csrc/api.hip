@@ -93,10 +93,10 @@ int check_hip(hipError_t e, const char* what) {
 
 // Default launch shapes, chosen by timing every shape at 16^3 x 32 and 32^3 x 64, Nc = 3,
 // Nv = 12 on MI355X:
-//   Wilson: row tiles (one x-row per work-group staged in LDS), 1 RHS per thread; FP64 and BF16
-//           with the RHS stride fixed at compile time for Nv = 12 (variant 4), FP32 with a runtime
-//           stride (variant 5, as fast).  Shapes the row tiles cannot take fall back to direct
-//           loads with one hop per iteration.
+//   Wilson: row tiles (one x-row per work-group staged in LDS), 1 RHS per thread, each
+//           direction's links staged in LDS beside the row and the RHS stride fixed for Nv = 12
+//           (variant 8; other Nv run as variant 5).  Shapes the row tiles cannot take fall back to
+//           direct loads with one hop per iteration.
 //   staggered: row tiles, 2 RHS/thread (direct loads with the hops unrolled where a row does not fit)
 //   Brillouin: 1 RHS/thread; FP32 and BF16 row tiles (27 row copies per x-row, link windows in
 //              LDS), FP64 direct loads (the row tile spills registers in FP64)
@@ -122,7 +122,7 @@ int choose_rb(dirac_op op, dirac_prec prec, int nc, int nv) {
 int choose_variant(dirac_op op, dirac_prec prec) {
     const int o = g_variant_override[op][prec];
     if (o > 0) return o;
-    if (op == DIRAC_WILSON) return prec == DIRAC_FP32 ? 5 : 4;
+    if (op == DIRAC_WILSON) return 8;
     if (op == DIRAC_BRILLOUIN) return prec == DIRAC_FP64 ? 1 : 4;
     return 4;  // staggered
 }
@@ -359,7 +359,7 @@ int dirac_set_launch_shape(dirac_op op, dirac_prec prec, int rb, int variant) {
     const int maxrb = op == DIRAC_BRILLOUIN ? 2 : 4;
     if (rb != 0 && rb != 1 && rb != 2 && rb != 4) return fail(DIRAC_EINVAL, "rb must be 0, 1, 2 or 4");
     if (rb > maxrb) return fail(DIRAC_EUNSUPPORTED, "rb not instantiated for this operator");
-    if (variant < 0 || variant > 7) return fail(DIRAC_EINVAL, "variant must be 0..7");
+    if (variant < 0 || variant > 8) return fail(DIRAC_EINVAL, "variant must be 0..8");
     g_rb_override[op][prec] = rb;
     g_variant_override[op][prec] = variant;
     return DIRAC_OK;

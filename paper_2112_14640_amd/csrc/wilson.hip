@@ -415,7 +415,7 @@ __global__ __launch_bounds__(512) void wilson_lds_kernel(const typename P::G* __
 // loads of one direction overlap the arithmetic of the previous one.  The output tile leaves
 // through LDS as one contiguous store.
 
-template <int NC, int RB, bool DAG, class P, int NVC>
+template <int NC, int RB, bool DAG, class P, int NVC, bool LL>
 __global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* __restrict__ U,
                                                           const typename P::S* __restrict__ in,
                                                           typename P::S* __restrict__ out, typename P::R diag,
@@ -467,6 +467,34 @@ __global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* _
         return reinterpret_cast<const S*>(rtile + jj * (rt.units + 1)) + rg * RB;
     };
 
+    // LL: the links of the direction being consumed are staged in LDS after the row tile, one
+    // N_c x N_c block per site of the row (forward hops: the row's own links; backward hops: the
+    // neighbour row's, used as adjoints), copied alongside the row; each thread moves at most LPER
+    // complex entries (NVC > 0).  Otherwise every thread loads its own link one direction ahead.
+    using G = typename P::G;
+    constexpr int NRG = NVC > 0 ? NVC / RB : 1;
+    constexpr int LPER = LL ? (L + NRG - 1) / NRG : 1;
+    G* lwin = reinterpret_cast<G*>(rtile + rt.S * (rt.units + 1));
+    const uint32_t nlink = static_cast<uint32_t>(rt.S) * L;
+    G lpre[LPER];
+    auto lfetch = [&](int64_t lrow, int mu) __attribute__((always_inline)) {
+#pragma unroll
+        for (int k = 0; k < LPER; ++k) {
+            const uint32_t u = k * static_cast<uint32_t>(rt.threads) + tt;
+            if (u < nlink) {
+                const uint32_t sx = u / L;
+                lpre[k] = U[((lrow + sx) * 4 + mu) * L + (u - sx * L)];
+            }
+        }
+    };
+    auto lstash = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int k = 0; k < LPER; ++k) {
+            const uint32_t u = k * static_cast<uint32_t>(rt.threads) + tt;
+            if (u < nlink) lwin[u] = lpre[k];
+        }
+    };
+
     cx<R> acc[RB][NC][4];
     constexpr int SF = DAG ? 1 : -1;  // forward projector 1 + SF g_mu
     // Links are loaded one direction ahead and before the next row copy: loads complete in issue
@@ -475,12 +503,23 @@ __global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* _
     const int xm = x == 0 ? g.nx - 1 : x - 1;
     cx<R> lxp[NC][NC], lxm[NC][NC], lnext[NC][NC];
     fetch(rowsite);
-    load_link<NC, false, P>(lxp, U + (site * 4 + 0) * L);
-    load_link<NC, true, P>(lxm, U + ((rowsite + xm) * 4 + 0) * L);
+    if constexpr (LL) {
+        lfetch(rowsite, 0);
+    } else {
+        load_link<NC, false, P>(lxp, U + (site * 4 + 0) * L);
+        load_link<NC, true, P>(lxm, U + ((rowsite + xm) * 4 + 0) * L);
+    }
     stash();
+    if constexpr (LL) lstash();
     __syncthreads();
     fetch(row_neighbour_start(pos, 0, g));
-    load_link<NC, false, P>(lnext, U + (site * 4 + 1) * L);
+    if constexpr (LL) {
+        lfetch(rowsite, 1);
+        load_link<NC, false, P>(lxp, lwin + x * L);
+        load_link<NC, true, P>(lxm, lwin + xm * L);
+    } else {
+        load_link<NC, false, P>(lnext, U + (site * 4 + 1) * L);
+    }
     // each transported half spinor enters the sum with -1/2 (+1/2 across the antiperiodic t
     // boundary) as the multiplier of the rebuild's multiply-adds
     if (active) {
@@ -499,24 +538,30 @@ __global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* _
         constexpr bool BACK = decltype(back_c)::value;
         constexpr int DIR = 2 * (MU - 1) + (BACK ? 1 : 0);
         cx<R> lcur[NC][NC];
+        if constexpr (!LL) {
 #pragma unroll
-        for (int a = 0; a < NC; ++a)
+            for (int a = 0; a < NC; ++a)
 #pragma unroll
-            for (int b = 0; b < NC; ++b) lcur[a][b] = lnext[a][b];
+                for (int b = 0; b < NC; ++b) lcur[a][b] = lnext[a][b];
+        }
         __syncthreads();
         stash();
+        if constexpr (LL) lstash();
         __syncthreads();
         if constexpr (DIR < 5) {
             constexpr int ND = DIR + 1;
             constexpr int NMU = ND / 2 + 1;
             const int64_t nrow = row_neighbour_start(pos, ND, g);
             fetch(nrow);
-            if constexpr (ND % 2 == 0) {
+            if constexpr (LL) {
+                lfetch(ND % 2 == 0 ? rowsite : nrow, NMU);
+            } else if constexpr (ND % 2 == 0) {
                 load_link<NC, false, P>(lnext, U + (site * 4 + NMU) * L);
             } else {
                 load_link<NC, true, P>(lnext, U + ((nrow + x) * 4 + NMU) * L);
             }
         }
+        if constexpr (LL) load_link<NC, BACK, P>(lcur, lwin + x * L);
         if (active) {
             const bool wrap = MU == 3 && g.apbc && ct == (BACK ? 0 : g.nt - 1);  // fermion sign
             hop_with<NC, RB, MU, (BACK ? -SF : SF), P, NVC>(acc, lcur, at(j), nv,
@@ -573,7 +618,10 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
     rt.magic_row_units = div_magic(rt.row_units);
     if (!row_order(a.variant, a.g, rt)) return false;
     const int block = (rt.threads + 63) / 64 * 64;
-    const size_t lds = row_tile_lds(rt.S, units);
+    size_t lds = row_tile_lds(rt.S, units);
+    // variant 8 also stages each direction's links: N_c^2 entries per site after the row tile
+    const size_t lds_ll = lds + (static_cast<size_t>(rt.S) * NC * NC * sizeof(typename P::G) + 15) / 16 * 16;
+    const bool ll = a.variant == 8 && a.nv == 12 && RB == 1 && lds_ll <= kRowLdsCap && lds_ll <= max_lds_per_block();
     const dim3 grid(static_cast<unsigned>(grid_blocks_x8(rt.ntiles, 1)));
     using R = typename P::R;
     const R diag = static_cast<R>(4.0 + a.mass);
@@ -589,16 +637,22 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
         }
         hipLaunchKernelGGL(kern, grid, dim3(block), lds, st, U, in, out, diag, a.g, a.nv, rt);
     };
-    if (a.variant == 4 && a.nv == 12 && RB == 1) {  // the common multi-RHS count: constant offsets
+    if (ll) {  // links staged in LDS with the rows (nv = 12)
+        lds = lds_ll;
         if (a.dagger)
-            go(wilson_rows_kernel<NC, RB, true, P, 12>);
+            go(wilson_rows_kernel<NC, RB, true, P, 12, true>);
         else
-            go(wilson_rows_kernel<NC, RB, false, P, 12>);
+            go(wilson_rows_kernel<NC, RB, false, P, 12, true>);
+    } else if (a.variant == 4 && a.nv == 12 && RB == 1) {  // the common multi-RHS count: constant offsets
+        if (a.dagger)
+            go(wilson_rows_kernel<NC, RB, true, P, 12, false>);
+        else
+            go(wilson_rows_kernel<NC, RB, false, P, 12, false>);
     } else {  // runtime RHS stride
         if (a.dagger)
-            go(wilson_rows_kernel<NC, RB, true, P, 0>);
+            go(wilson_rows_kernel<NC, RB, true, P, 0, false>);
         else
-            go(wilson_rows_kernel<NC, RB, false, P, 0>);
+            go(wilson_rows_kernel<NC, RB, false, P, 0, false>);
     }
     return ok;
 }
@@ -636,7 +690,7 @@ bool launch_lds(const StencilArgs& a, hipStream_t st) {
 template <int NC, int RB, class P>
 void launch_rb(const StencilArgs& a, hipStream_t st) {
     using R = typename P::R;
-    if (a.variant >= 4 && a.variant <= 7) {
+    if (a.variant >= 4 && a.variant <= 8) {
         if (launch_rows<NC, RB, P>(a, st)) return;
         StencilArgs b = a;  // the row tile does not fit: direct loads, one hop per iteration
         b.variant = 3;

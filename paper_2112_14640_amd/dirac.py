@@ -420,7 +420,7 @@ def flops_per_site(op, nc: int) -> float:
 def set_launch_shape(op, prec, rb: int = 0, variant: int = 0):
     """Launch-shape knob of the stencil kernels: RHS per thread (0 = automatic) and variant
     (0 = automatic, 1 = direct global loads, 2 = LDS-staged site tiles, 3 = direct loads one hop per
-    iteration, 4..7 = row tiles; see include/dirac.h)."""
+    iteration, 4..8 = row tiles (8: Wilson with links staged in LDS); see include/dirac.h)."""
     if isinstance(prec, str):
         prec = {"fp64": L.FP64, "fp32": L.FP32, "bf16": L.BF16}[prec]
     L.check(L.load().dirac_set_launch_shape(_op(op), prec, rb, variant), "set_launch_shape")

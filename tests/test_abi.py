@@ -120,6 +120,8 @@ def test_blas_and_misc_validation():
     assert lib.dirac_set_launch_shape(L.BRILLOUIN, L.FP32, 4, 0) == L.EUNSUPPORTED
     assert lib.dirac_set_launch_shape(L.WILSON, L.FP32, 3, 0) == L.EINVAL
     assert lib.dirac_set_launch_shape(L.WILSON, L.FP32, 0, 0) == L.OK
+    assert lib.dirac_set_launch_shape(L.WILSON, L.FP32, 1, 9) == L.EINVAL
+    assert lib.dirac_set_launch_shape(L.WILSON, L.FP32, 0, 0) == L.OK
     out = C.c_double(0.0)
     assert lib.dirac_probe_copy(FAKE_A, FAKE_B, 100, 1, C.byref(out), None) == L.EINVAL  # not a multiple of 16
     assert lib.dirac_probe_copy(FAKE_A, FAKE_B, 1600, 0, C.byref(out), None) == L.EINVAL  # reps < 1

@@ -184,7 +184,7 @@ def test_free_field_plane_wave_16x32():
     assert col_rel_err(host(v), expect) < 1e-12
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("rb", [1, 2, 4])
 @pytest.mark.parametrize("op", ["wilson", "staggered", "brillouin"])
 def test_launch_shapes_agree(op, rb, variant):
@@ -216,7 +216,7 @@ ROW_CASES = [
 ]
 
 
-@pytest.mark.parametrize("variant", [4, 5, 6, 7])
+@pytest.mark.parametrize("variant", [4, 5, 6, 7, 8])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 @pytest.mark.parametrize("case", range(len(ROW_CASES)))
 def test_wilson_row_tiles(case, prec, variant):
