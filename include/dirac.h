@@ -212,11 +212,11 @@ int bicgstab_solve(dirac_op op, dirac_prec outer, dirac_prec inner, const void* 
  * 4 x 4 (y, z) blocks with t next; the RHS stride is a compile-time constant when nv = 12),
  * 5 the same with a runtime RHS stride, 6 the same in 8 x 8 (y, z) blocks, 7 t slabs (one per XCD) of
  * 4 x 4 blocks, 8 as 4 with each direction's links staged in LDS beside the row copy (nv = 12,
- * 1 RHS per thread; otherwise as 5).  Variant 8 is Wilson only (the other operators run it as
- * direct loads).  Brillouin: 4 row tiles (a work-group walks
- * the 27 neighbouring x-rows of its row, each staged in LDS with a window of three links per
- * site), anything else direct global loads.  Staggered: 4 row tiles as for Wilson (one x-row
- * per work-group, the six other neighbour rows staged in turn).
+ * 1 RHS per thread; otherwise as 5).  Brillouin: 4 row tiles (a work-group walks the 27
+ * neighbouring x-rows of its row, each staged in LDS with a window of three links per site),
+ * anything else direct global loads.  Staggered: 4 row tiles as for Wilson (one x-row per
+ * work-group, the six other neighbour rows staged in turn), 8 the same with each direction's links
+ * staged in LDS (at most two link entries per thread, else as 4), anything else direct loads.
  * Results agree to rounding whatever the shape.  Process-wide, not thread-safe. */
 int dirac_set_launch_shape(dirac_op op, dirac_prec prec, int rb, int variant);
 

@@ -97,7 +97,9 @@ int check_hip(hipError_t e, const char* what) {
 //           direction's links staged in LDS beside the row and the RHS stride fixed for Nv = 12
 //           (variant 8; other Nv run as variant 5).  Shapes the row tiles cannot take fall back to
 //           direct loads with one hop per iteration.
-//   staggered: row tiles, 2 RHS/thread (direct loads with the hops unrolled where a row does not fit)
+//   staggered: row tiles, 2 RHS/thread, FP32 and BF16 with each direction's links staged in LDS
+//              (variant 8), FP64 with per-thread link loads (variant 4: the staged form touches
+//              scratch in FP64); direct loads with the hops unrolled where a row does not fit
 //   Brillouin: 1 RHS/thread; FP32 and BF16 row tiles (27 row copies per x-row, link windows in
 //              LDS), FP64 direct loads (the row tile spills registers in FP64)
 // A shape that does not divide nv falls back to fewer RHS per thread.
@@ -124,7 +126,7 @@ int choose_variant(dirac_op op, dirac_prec prec) {
     if (o > 0) return o;
     if (op == DIRAC_WILSON) return 8;
     if (op == DIRAC_BRILLOUIN) return prec == DIRAC_FP64 ? 1 : 4;
-    return 4;  // staggered
+    return prec == DIRAC_FP64 ? 4 : 8;  // staggered
 }
 
 size_t solver_workspace_bytes(dirac_op op, int solver, dirac_prec outer, dirac_prec inner, int nc, int nv,

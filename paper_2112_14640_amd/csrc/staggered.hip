@@ -247,7 +247,7 @@ bool launch_lds(const StencilArgs& a, hipStream_t st) {
 // Row-tiled variant: one x-row (every RHS) per work-group, the rows one step along +-y, +-z,
 // +-t staged in LDS one at a time with contiguous loads of Unit (16 or 8 bytes), the next row copy
 // and its link in flight while the current direction is consumed (see the Wilson row kernel).
-template <int NC, int RB, bool DAG, class P, typename Unit>
+template <int NC, int RB, bool DAG, class P, typename Unit, bool LL>
 __global__ __launch_bounds__(512) void staggered_rows_kernel(const typename P::G* __restrict__ U,
                                                              const typename P::S* __restrict__ in,
                                                              typename P::S* __restrict__ out, typename P::R mass,
@@ -308,6 +308,31 @@ __global__ __launch_bounds__(512) void staggered_rows_kernel(const typename P::G
                     l[a][b] = v;
             }
     };
+    // LL: the links of the direction being consumed are staged in LDS after the row tile (one
+    // N_c x N_c block per site; forward hops the row's own links, backward hops the neighbour
+    // row's, used as adjoints), at most LPER complex entries per thread; otherwise every thread
+    // loads its own link one direction ahead.
+    constexpr int LPER = 2;
+    G* lwin = reinterpret_cast<G*>(sraw + (static_cast<size_t>(rt.S) * (rt.units + 1) * sizeof(Unit) + 15) / 16 * 16);
+    const uint32_t nlink = static_cast<uint32_t>(rt.S) * L;
+    G lpre[LPER];
+    auto lfetch = [&](int64_t lrow, int mu) __attribute__((always_inline)) {
+#pragma unroll
+        for (int k = 0; k < LPER; ++k) {
+            const uint32_t u = k * static_cast<uint32_t>(rt.threads) + tt;
+            if (u < nlink) {
+                const uint32_t sx = u / L;
+                lpre[k] = U[((lrow + sx) * 4 + mu) * L + (u - sx * L)];
+            }
+        }
+    };
+    auto lstash = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int k = 0; k < LPER; ++k) {
+            const uint32_t u = k * static_cast<uint32_t>(rt.threads) + tt;
+            if (u < nlink) lwin[u] = lpre[k];
+        }
+    };
     cx<R> acc[RB][NC];
     const R half = DAG ? R(-0.5) : R(0.5);
     // eta_mu(n) = (-1)^(x_0 + ... + x_{mu-1})
@@ -317,12 +342,23 @@ __global__ __launch_bounds__(512) void staggered_rows_kernel(const typename P::G
     const int xm = x == 0 ? g.nx - 1 : x - 1;
     cx<R> lxp[NC][NC], lxm[NC][NC], lnext[NC][NC];
     fetch(rowsite);
-    load_link(lxp, U + (site * 4 + 0) * L, false);
-    load_link(lxm, U + ((rowsite + xm) * 4 + 0) * L, true);
+    if constexpr (LL) {
+        lfetch(rowsite, 0);
+    } else {
+        load_link(lxp, U + (site * 4 + 0) * L, false);
+        load_link(lxm, U + ((rowsite + xm) * 4 + 0) * L, true);
+    }
     stash();
+    if constexpr (LL) lstash();
     __syncthreads();
     fetch(row_neighbour_start(pos, 0, g));
-    load_link(lnext, U + (site * 4 + 1) * L, false);
+    if constexpr (LL) {
+        lfetch(rowsite, 1);
+        load_link(lxp, lwin + x * L, false);
+        load_link(lxm, lwin + xm * L, true);
+    } else {
+        load_link(lnext, U + (site * 4 + 1) * L, false);
+    }
     auto hop_acc = [&](const cx<R> (&l)[NC][NC], const S* nb, R scale) __attribute__((always_inline)) {
 #pragma unroll
         for (int k = 0; k < RB; ++k) {
@@ -349,23 +385,29 @@ __global__ __launch_bounds__(512) void staggered_rows_kernel(const typename P::G
         constexpr bool BACK = decltype(back_c)::value;
         constexpr int DIR = 2 * (MU - 1) + (BACK ? 1 : 0);
         cx<R> lcur[NC][NC];
+        if constexpr (!LL) {
 #pragma unroll
-        for (int a = 0; a < NC; ++a)
+            for (int a = 0; a < NC; ++a)
 #pragma unroll
-            for (int b = 0; b < NC; ++b) lcur[a][b] = lnext[a][b];
+                for (int b = 0; b < NC; ++b) lcur[a][b] = lnext[a][b];
+        }
         __syncthreads();
         stash();
+        if constexpr (LL) lstash();
         __syncthreads();
         if constexpr (DIR < 5) {
             constexpr int ND = DIR + 1;
             constexpr int NMU = ND / 2 + 1;
             const int64_t nrow = row_neighbour_start(pos, ND, g);
             fetch(nrow);
-            if constexpr (ND % 2 == 0)
+            if constexpr (LL)
+                lfetch(ND % 2 == 0 ? rowsite : nrow, NMU);
+            else if constexpr (ND % 2 == 0)
                 load_link(lnext, U + (site * 4 + NMU) * L, false);
             else
                 load_link(lnext, U + ((nrow + x) * 4 + NMU) * L, true);
         }
+        if constexpr (LL) load_link(lcur, lwin + x * L, BACK);
         if (active) {
             R sc = BACK ? -eta[MU] : eta[MU];
             if (MU == 3 && g.apbc && ct == (BACK ? 0 : g.nt - 1)) sc = -sc;  // fermion sign
@@ -432,12 +474,24 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
         auto U = static_cast<const typename P::G*>(a.gauge);
         auto in = static_cast<const S*>(a.in);
         auto out = static_cast<S*>(a.out);
-        if (a.dagger)
-            hipLaunchKernelGGL((staggered_rows_kernel<NC, RB, true, P, Unit>), grid, dim3(block), lds, st, U, in, out,
-                               m, a.g, a.nv, rt);
-        else
-            hipLaunchKernelGGL((staggered_rows_kernel<NC, RB, false, P, Unit>), grid, dim3(block), lds, st, U, in,
+        // variant 8: each direction's links staged in LDS after the row tile (two entries per thread
+        // at most)
+        const size_t lds_ll = (lds + 15) / 16 * 16 + static_cast<size_t>(a.g.nx) * NC * NC * sizeof(typename P::G);
+        const bool ll = a.variant == 8 && static_cast<int64_t>(a.g.nx) * NC * NC <= 2 * threads && lds_ll <= 64 * 1024;
+        if (ll) {
+            if (a.dagger)
+                hipLaunchKernelGGL((staggered_rows_kernel<NC, RB, true, P, Unit, true>), grid, dim3(block), lds_ll, st,
+                                   U, in, out, m, a.g, a.nv, rt);
+            else
+                hipLaunchKernelGGL((staggered_rows_kernel<NC, RB, false, P, Unit, true>), grid, dim3(block), lds_ll, st,
+                                   U, in, out, m, a.g, a.nv, rt);
+        } else if (a.dagger) {
+            hipLaunchKernelGGL((staggered_rows_kernel<NC, RB, true, P, Unit, false>), grid, dim3(block), lds, st, U, in,
                                out, m, a.g, a.nv, rt);
+        } else {
+            hipLaunchKernelGGL((staggered_rows_kernel<NC, RB, false, P, Unit, false>), grid, dim3(block), lds, st, U,
+                               in, out, m, a.g, a.nv, rt);
+        }
         return true;
     }
 }
@@ -445,7 +499,7 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
 template <int NC, int RB, class P>
 void launch_rb(const StencilArgs& a, hipStream_t st) {
     using R = typename P::R;
-    if (a.variant == 4 && launch_rows<NC, RB, P>(a, st)) return;
+    if ((a.variant == 4 || a.variant == 8) && launch_rows<NC, RB, P>(a, st)) return;
     if (use_lds_variant(a, false) && launch_lds<NC, RB, P>(a, st)) return;
     const int block = 256;
     const int64_t threads = a.g.vol * (a.nv / RB);

@@ -277,15 +277,17 @@ STAGGERED_ROW_CASES = [
 ]
 
 
+@pytest.mark.parametrize("variant", [4, 8])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 @pytest.mark.parametrize("case", range(len(STAGGERED_ROW_CASES)))
-def test_staggered_row_tiles(case, prec):
-    """The row-tiled staggered kernel (1 and 2 RHS per thread, where a row fits) against the oracle."""
+def test_staggered_row_tiles(case, prec, variant):
+    """The row-tiled staggered kernel (1 and 2 RHS per thread, where a row fits; links loaded per
+    thread (4) or staged in LDS (8)) against the oracle."""
     dims, nc, nv, apbc = STAGGERED_ROW_CASES[case]
     gauge, u = _inputs("staggered", dims, nc, nv, seed=80 + case)
     for rb in (1, 2):
         try:
-            dirac.set_launch_shape("staggered", prec, rb, 4)
+            dirac.set_launch_shape("staggered", prec, rb, variant)
             for dagger in (False, True):
                 v, g_in, u_in = _run("staggered", prec, gauge, u, 0.06, apbc, dagger)
                 err = col_rel_err(v, ORACLE[("staggered", dagger)](g_in, u_in, 0.06, apbc))
