@@ -268,6 +268,38 @@ __global__ __launch_bounds__(256) void k_xp_update(SX* __restrict__ x, SP* __res
     }
 }
 
+// x += alpha p ; p = r + beta p ; partial <r, p> of the new p as stored (the line-search numerator
+// of the next step; reads and writes nothing beyond k_xp_update)
+template <typename SX, typename SP, typename SR>
+__global__ __launch_bounds__(kReduceThreads) void k_xp_update_dot(SX* __restrict__ x, SP* __restrict__ p,
+                                                                   const SR* __restrict__ r,
+                                                                   const double2* __restrict__ alpha,
+                                                                   const double2* __restrict__ beta, int64_t nrows,
+                                                                   int nv, double* __restrict__ partial) {
+    const RowLane rl = row_lane(nv);
+    double acc[2] = {0.0, 0.0};
+    if (rl.roff < rl.rpb) {
+        const double2 al = alpha[rl.rhs], be = beta[rl.rhs];
+        const int64_t step = static_cast<int64_t>(gridDim.x) * rl.rpb;
+#pragma unroll 4
+        for (int64_t row = static_cast<int64_t>(blockIdx.x) * rl.rpb + rl.roff; row < nrows; row += step) {
+            const int64_t i = row * nv + rl.rhs;
+            const cx<double> pv = ldd(p + i);
+            cx<double> xv = ldd(x + i);
+            cfma(xv, cx<double>{al.x, al.y}, pv);
+            std_(x + i, xv);
+            const cx<double> rv = ldd(r + i);
+            cx<double> np = rv;
+            cfma(np, cx<double>{be.x, be.y}, pv);
+            std_(p + i, np);
+            const cx<double> ps = stored_value<SP>(np);  // <r, p> of p as stored
+            acc[0] += rv.re * ps.re + rv.im * ps.im;
+            acc[1] += rv.re * ps.im - rv.im * ps.re;
+        }
+    }
+    block_partials<2>(acc, nv, rl, partial);
+}
+
 // BiCGstab: x += alpha p + omega s ; r = s - omega t ; partial ||r||^2
 template <typename S>
 __global__ __launch_bounds__(kReduceThreads) void k_bicg_xr(S* __restrict__ x, const S* __restrict__ p,
@@ -487,6 +519,26 @@ int fused_xp_update(dirac_prec px, void* x, dirac_prec pp, void* p, dirac_prec p
                                    static_cast<SP*>(p), static_cast<const SR*>(r),
                                    reinterpret_cast<const double2*>(alpha), reinterpret_cast<const double2*>(beta), n,
                                    nv);
+                return DIRAC_OK;
+            });
+        });
+    });
+}
+
+int fused_xp_update_dot(dirac_prec px, void* x, dirac_prec pp, void* p, dirac_prec prr, const void* r,
+                        const double* alpha, const double* beta, int64_t nrows, int nv, double* partial, double* rp,
+                        hipStream_t st) {
+    return with_prec(px, [&](auto tx) {
+        return with_prec(pp, [&](auto tp) {
+            return with_prec(prr, [&](auto trr) {
+                using SX = typename decltype(tx)::type;
+                using SP = typename decltype(tp)::type;
+                using SR = typename decltype(trr)::type;
+                hipLaunchKernelGGL((k_xp_update_dot<SX, SP, SR>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, st,
+                                   static_cast<SX*>(x), static_cast<SP*>(p), static_cast<const SR*>(r),
+                                   reinterpret_cast<const double2*>(alpha), reinterpret_cast<const double2*>(beta),
+                                   nrows, nv, partial);
+                finalize(partial, 2, nv, rp, st);
                 return DIRAC_OK;
             });
         });

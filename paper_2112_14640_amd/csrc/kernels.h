@@ -63,6 +63,10 @@ int fused_r_update(dirac_prec pr, void* r, dirac_prec pq, const void* q, const d
 // x += alpha p ; p = r + beta p   (x precision px; r, p precision pp)
 int fused_xp_update(dirac_prec px, void* x, dirac_prec pp, void* p, dirac_prec prr, const void* r, const double* alpha,
                     const double* beta, int64_t nrows, int nv, hipStream_t st);
+// x += alpha p ; p = r + beta p ; rp = <r, p> of the new p as stored (2 nv doubles, re/im per RHS)
+int fused_xp_update_dot(dirac_prec px, void* x, dirac_prec pp, void* p, dirac_prec prr, const void* r,
+                        const double* alpha, const double* beta, int64_t nrows, int nv, double* partial, double* rp,
+                        hipStream_t st);
 // y = b - y  (residual from A x stored in y)
 int blas_bminus(dirac_prec pb, const void* b, dirac_prec py, void* y, int64_t nrows, int nv, hipStream_t st);
 // r = b - q (all complex elements, any precisions)

@@ -83,6 +83,20 @@ __global__ void k_cg_alpha(const double* __restrict__ pq, const double* __restri
     alpha[2 * i + 1] = 0.0;
 }
 
+// Line-search step of the reliable-update inner CG: alpha = <p, r> / p^+ A p = conj(<r, p>) / ||D p||^2,
+// the exact minimiser along the stored direction p of the A-norm of the error.  With p stored in a
+// lower precision than r, <r, p> drifts away from ||r||^2 (the deviation is carried forward by beta)
+// and the textbook ||r||^2 / p^+ A p can then overshoot and make the recurrence diverge.
+__global__ void k_cg_alpha_ls(const double* __restrict__ pq, const double* __restrict__ rp,
+                              const double* __restrict__ mask, double* __restrict__ alpha, int nv) {
+    const int i = threadIdx.x;
+    if (i >= nv) return;
+    const double d = pq[i];
+    const bool ok = mask[i] != 0.0 && d > 0.0 && std::isfinite(d);
+    alpha[2 * i] = ok ? rp[2 * i] / d : 0.0;
+    alpha[2 * i + 1] = ok ? -rp[2 * i + 1] / d : 0.0;
+}
+
 // beta = rr_new / rr (active RHS), then rr = rr_new
 __global__ void k_cg_beta(const double* __restrict__ rr_new, double* __restrict__ rr, const double* __restrict__ mask,
                           double* __restrict__ beta, int nv) {
@@ -112,6 +126,7 @@ struct Scalars {
     double* beta = nullptr;     // 2nv
     double* cplx = nullptr;     // 8nv general complex scratch (BiCGstab)
     double* mask = nullptr;     // nv (1 active, 0 frozen)
+    double* rp = nullptr;       // 2nv: <r, p> (reliable-update line search)
     double* hbuf = nullptr;     // pinned host, 16 nv doubles
     void carve(Carver& c, int nv_) {
         nv = nv_;
@@ -124,6 +139,7 @@ struct Scalars {
         beta = static_cast<double*>(c.take(2 * nv * sizeof(double)));
         cplx = static_cast<double*>(c.take(8 * nv * sizeof(double)));
         mask = static_cast<double*>(c.take(nv * sizeof(double)));
+        rp = static_cast<double*>(c.take(2 * nv * sizeof(double)));
     }
 };
 
@@ -383,6 +399,9 @@ int cg_reliable(const OpCtx& o, const RUVecs& v, const Rules& ru, double delta, 
     };
     if ((rc = restart_inner())) return rc;
     if ((rc = blas_cast(F32, v.r, v.pin, v.p, n, st))) return rc;
+    // <r, p> of the stored p: the numerator of the line-search step
+    if ((rc = blas_dot(F32, v.r, v.pin, v.p, o.nrows, nv, s.partial, s.rp, st))) return rc;
+    // rmax: largest inner residual norm since the last replacement (Sleijpen and van der Vorst)
     std::vector<double> rmax(nv), best(nv);
     for (int i = 0; i < nv; ++i) rmax[i] = best[i] = std::sqrt(rt[i]);
     std::vector<int> no_progress(nv, 0);
@@ -396,7 +415,7 @@ int cg_reliable(const OpCtx& o, const RUVecs& v, const Rules& ru, double delta, 
         ++it;
         if ((rc = apply_normal(o, v.pin, v.g_lo, v.p, v.q, v.t, st))) return rc;
         if ((rc = blas_norm2(v.pin, v.t, o.nrows, nv, s.partial, s.pq, st))) return rc;  // ||D p||^2
-        hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, st, s.pq, s.rr, s.mask, s.alpha, nv);
+        hipLaunchKernelGGL(k_cg_alpha_ls, dim3(1), dim3(256), 0, st, s.pq, s.rp, s.mask, s.alpha, nv);
         if ((rc = fused_r_update(F32, v.r, v.pin, v.q, s.alpha, o.nrows, nv, s.partial, s.rr_new, st))) return rc;
         if ((rc = d2h(h, s.rr_new, nv, st))) return rc;
         std::vector<double> rn(h, h + nv);
@@ -405,12 +424,16 @@ int cg_reliable(const OpCtx& o, const RUVecs& v, const Rules& ru, double delta, 
         bool suggest = true;
         for (int i = 0; i < nv; ++i) {
             if (active[i] == 0.0) continue;
-            if (std::sqrt(rn[i]) < delta * rmax[i]) update = true;
-            if (std::sqrt(rn[i]) > goal[i]) suggest = false;
+            const double r_in = std::sqrt(rn[i]);
+            rmax[i] = std::max(rmax[i], r_in);
+            if (r_in < delta * rmax[i]) update = true;
+            if (r_in > goal[i]) suggest = false;
         }
         update = update || suggest;
         hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, st, s.rr_new, s.rr, s.mask, s.beta, nv);
-        if ((rc = fused_xp_update(F32, v.xl, v.pin, v.p, F32, v.r, s.alpha, s.beta, o.nrows, nv, st))) return rc;
+        if ((rc = fused_xp_update_dot(F32, v.xl, v.pin, v.p, F32, v.r, s.alpha, s.beta, o.nrows, nv, s.partial, s.rp,
+                                      st)))
+            return rc;
         if (!update) continue;
         // x += xl in FP64, true residual, replace the inner residual (keep p)
         for (int i = 0; i < nv; ++i) {
@@ -454,6 +477,8 @@ int cg_reliable(const OpCtx& o, const RUVecs& v, const Rules& ru, double delta, 
             break;
         }
         if ((rc = restart_inner())) return rc;
+        // p is kept; its line-search numerator is taken against the replaced residual
+        if ((rc = blas_dot(F32, v.r, v.pin, v.p, o.nrows, nv, s.partial, s.rp, st))) return rc;
     }
     res.iters = it;
     return DIRAC_OK;

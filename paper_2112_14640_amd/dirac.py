@@ -62,13 +62,25 @@ def _stream() -> int:
     return torch.cuda.current_stream().cuda_stream
 
 
-def _require(t: torch.Tensor, name: str):
+def _require(t: torch.Tensor, name: str, device=None):
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a tensor")
     if not t.is_cuda:
         raise ValueError(f"{name} must be a GPU tensor (libdirac has no CPU path)")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+
+
+def _require_like(t: torch.Tensor, name: str, ref: torch.Tensor):
+    """t must be a contiguous tensor on ref's device with ref's exact shape and dtype (an output or
+    scratch buffer the library writes as many bytes into as ref holds)."""
+    _require(t, name, ref.device)
+    if tuple(t.shape) != tuple(ref.shape):
+        raise ValueError(f"{name} shape {tuple(t.shape)} != {tuple(ref.shape)}")
+    if t.dtype != ref.dtype:
+        raise TypeError(f"{name} dtype {t.dtype} != {ref.dtype}")
 
 
 @dataclass
@@ -109,8 +121,8 @@ def geometry(op, u: torch.Tensor, antiperiodic_t=True) -> Geometry:
     return Geometry(op, prec, nc, s[-1], (nx, ny, nz, nt), antiperiodic_t)
 
 
-def _check_gauge(g: Geometry, gauge: torch.Tensor, name="gauge"):
-    _require(gauge, name)
+def _check_gauge(g: Geometry, gauge: torch.Tensor, name="gauge", device=None):
+    _require(gauge, name, device)
     nx, ny, nz, nt = g.dims
     dirs = 40 if g.op == L.BRILLOUIN else 4
     want = (nt, nz, ny, nx, dirs, g.nc, g.nc)
@@ -123,13 +135,11 @@ def _check_gauge(g: Geometry, gauge: torch.Tensor, name="gauge"):
 def _apply(fn, op, gauge, u, mass, antiperiodic_t, out):
     _require(u, "u")
     g = geometry(op, u, antiperiodic_t)
-    _check_gauge(g, gauge)
+    _check_gauge(g, gauge, device=u.device)
     if out is None:
         out = torch.empty_like(u)
     else:
-        _require(out, "out")
-        if out.shape != u.shape or out.dtype != u.dtype:
-            raise ValueError("out must match u in shape and dtype")
+        _require_like(out, "out", u)
     lib = L.load()
     d = g.cdims()
     L.check(getattr(lib, fn)(g.op, g.prec, _ptr(gauge), _ptr(u), _ptr(out), float(mass), g.nc, g.nv, C.byref(d),
@@ -151,9 +161,11 @@ def apply_normal(op, gauge, u, mass, antiperiodic_t=True, out=None, tmp=None):
     """v = D^dagger D u (through a scratch vector)."""
     _require(u, "u")
     g = geometry(op, u, antiperiodic_t)
-    _check_gauge(g, gauge)
+    _check_gauge(g, gauge, device=u.device)
     out = torch.empty_like(u) if out is None else out
     tmp = torch.empty_like(u) if tmp is None else tmp
+    _require_like(out, "out", u)
+    _require_like(tmp, "tmp", u)
     d = g.cdims()
     L.check(L.load().dirac_apply_normal(g.op, g.prec, _ptr(gauge), _ptr(u), _ptr(out), _ptr(tmp), float(mass), g.nc,
                                         g.nv, C.byref(d), _stream()), "dirac_apply_normal")
@@ -171,6 +183,10 @@ def brillouin_links(U, antiperiodic_t=True, out=None):
     nt, nz, ny, nx, _, nc, _ = U.shape
     if out is None:
         out = torch.empty((nt, nz, ny, nx, 40, nc, nc), dtype=U.dtype, device=U.device)
+    else:
+        _require(out, "out", U.device)
+        if tuple(out.shape) != (nt, nz, ny, nx, 40, nc, nc) or out.dtype != U.dtype:
+            raise ValueError("out must be a (Nt,Nz,Ny,Nx,40,Nc,Nc) tensor of U's dtype")
     d = L.Dims()
     for i, n in enumerate((nx, ny, nz, nt)):
         d.n[i] = n
@@ -182,8 +198,9 @@ def brillouin_links(U, antiperiodic_t=True, out=None):
 
 def force(op, U, psi, chi, coeff=1.0, antiperiodic_t=True, out=None):
     """out += coeff * d Re(psi^dagger D chi) / dU (torch's complex-gradient convention); FP64."""
-    for t, n in ((U, "U"), (psi, "psi"), (chi, "chi")):
-        _require(t, n)
+    _require(psi, "psi")
+    for t, n in ((U, "U"), (chi, "chi")):
+        _require(t, n, psi.device)
     g = geometry(op, psi, antiperiodic_t)
     if g.prec != L.FP64 or chi.dtype != torch.complex128 or U.dtype != torch.complex128:
         raise TypeError("force is FP64 (complex128) only")
@@ -191,6 +208,7 @@ def force(op, U, psi, chi, coeff=1.0, antiperiodic_t=True, out=None):
         raise ValueError("psi and chi must have the same shape")
     _check_gauge(g, U, "U")
     out = torch.zeros_like(U) if out is None else out
+    _require_like(out, "out", U)
     d = g.cdims()
     L.check(L.load().dirac_force(g.op, _ptr(U), _ptr(psi), _ptr(chi), _ptr(out), float(coeff), g.nc, g.nv,
                                  C.byref(d), _stream()), "dirac_force")
@@ -200,11 +218,14 @@ def force(op, U, psi, chi, coeff=1.0, antiperiodic_t=True, out=None):
 def project_su(U, g, out=None):
     """su(Nc) force (i/2)(U g^+ - g U^+) - trace/Nc, FP64."""
     _require(U, "U")
-    _require(g, "g")
+    _require(g, "g", U.device)
     if U.dtype != torch.complex128 or g.dtype != torch.complex128 or U.shape != g.shape:
         raise TypeError("U and g must be complex128 tensors of the same shape")
+    if U.dim() < 2 or U.shape[-1] != U.shape[-2]:
+        raise ValueError("U must end in a square (Nc, Nc) matrix axis")
     nc = U.shape[-1]
     out = torch.empty_like(U) if out is None else out
+    _require_like(out, "out", U)
     L.check(L.load().dirac_project_su(_ptr(U), _ptr(g), _ptr(out), nc, U.numel() // (nc * nc), _stream()),
             "dirac_project_su")
     return out
@@ -241,7 +262,7 @@ def norm2(x: torch.Tensor) -> torch.Tensor:
 def dot(x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
     """<x_i, y_i> = sum conj(x) y per RHS (complex128, length Nv)."""
     _require(x, "x")
-    _require(y, "y")
+    _require(y, "y", x.device)
     px, py = vector_prec(x), vector_prec(y)
     nrows, nv = _rows(x, px)
     if _rows(y, py) != (nrows, nv):
@@ -265,7 +286,7 @@ def _coef(a, nv, device):
 def caxpy(a, x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
     """y_i += a_i x_i in place (the paper's "incr")."""
     _require(x, "x")
-    _require(y, "y")
+    _require(y, "y", x.device)
     px, py = vector_prec(x), vector_prec(y)
     nrows, nv = _rows(x, px)
     if _rows(y, py) != (nrows, nv):
@@ -278,7 +299,7 @@ def caxpy(a, x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
 def cxpay(x: torch.Tensor, a, y: torch.Tensor) -> torch.Tensor:
     """y_i = x_i + a_i y_i in place (the paper's "anti")."""
     _require(x, "x")
-    _require(y, "y")
+    _require(y, "y", x.device)
     px, py = vector_prec(x), vector_prec(y)
     nrows, nv = _rows(x, px)
     if _rows(y, py) != (nrows, nv):
@@ -317,6 +338,7 @@ def gamma5(op, x: torch.Tensor, antiperiodic_t=True, out=None) -> torch.Tensor:
     _require(x, "x")
     g = geometry(op, x, antiperiodic_t)
     out = torch.empty_like(x) if out is None else out
+    _require_like(out, "out", x)
     d = g.cdims()
     L.check(L.load().dirac_gamma5(g.op, g.prec, _ptr(x), _ptr(out), g.nc, g.nv, C.byref(d), _stream()), "gamma5")
     return out
@@ -339,15 +361,21 @@ class SolveInfo:
 def _solve(fn, solver, op, gauge, b, mass, x0, tol, maxit, inner, gauge_lo, antiperiodic_t, history, opts):
     _require(b, "b")
     g = geometry(op, b, antiperiodic_t)
-    _check_gauge(g, gauge)
+    _check_gauge(g, gauge, device=b.device)
     outer = g.prec
     inner_p = outer if inner is None else {"fp64": L.FP64, "fp32": L.FP32, "bf16": L.BF16}[inner]
     if inner_p != outer:
         if gauge_lo is None:
             raise ValueError("mixed precision needs gauge_lo (complex64 links)")
         gl = Geometry(g.op, inner_p, g.nc, g.nv, g.dims, g.antiperiodic_t)
-        _check_gauge(gl, gauge_lo, "gauge_lo")
-    x = torch.zeros_like(b) if x0 is None else x0.clone()
+        _check_gauge(gl, gauge_lo, "gauge_lo", device=b.device)
+    x = torch.zeros_like(b)
+    if x0 is not None:
+        if not isinstance(x0, torch.Tensor):
+            raise TypeError("x0 must be a tensor")
+        if x0.device != b.device or tuple(x0.shape) != tuple(b.shape) or x0.dtype != b.dtype:
+            raise ValueError("x0 must match b in device, shape and dtype")
+        x.copy_(x0)
     lib = L.load()
     d = g.cdims()
     nbytes = lib.dirac_solver_workspace_bytes(g.op, solver, outer, inner_p, g.nc, g.nv, C.byref(d))
@@ -394,7 +422,7 @@ def bicgstab(op, gauge, b, mass, x0=None, tol=1e-10, maxit=1000, inner=None, gau
 def probe_copy(src: torch.Tensor, dst: torch.Tensor, reps: int = 10) -> float:
     """Sustained device copy rate (read + written bytes per second) over src -> dst (same byte size)."""
     _require(src, "src")
-    _require(dst, "dst")
+    _require(dst, "dst", src.device)
     nbytes = src.numel() * src.element_size()
     if dst.numel() * dst.element_size() != nbytes:
         raise ValueError("probe_copy: src and dst must have the same byte size")

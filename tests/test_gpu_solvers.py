@@ -4,7 +4,7 @@ import pytest
 import torch
 
 import synthetic_inputs as si
-from oracle.brillouin import brillouin_apply, brillouin_links
+from oracle.brillouin import brillouin_apply, brillouin_apply_dagger, brillouin_links
 from oracle.solvers import cg as oracle_cg
 from oracle.staggered import staggered_apply, staggered_apply_dagger
 from oracle.wilson import wilson_apply, wilson_apply_dagger
@@ -58,8 +58,6 @@ def test_cg_brillouin_fp64():
     x, info = dirac.cg("brillouin", to_dev(W), to_dev(b), MASS, tol=1e-10, maxit=2000)
     assert info.reason == "converged"
     xh = host(x)
-    r = b - brillouin_apply(W, brillouin_apply(W, xh, MASS), MASS) if False else None
-    from oracle.brillouin import brillouin_apply_dagger
     r = b - brillouin_apply_dagger(W, brillouin_apply(W, xh, MASS), MASS)
     assert np.all(_colres(r, b) < 1e-10)
 
