@@ -14,6 +14,8 @@ but with no blocking, fusion or reordering beyond what the definitions state:
 * ``wilson``     D_W (Eqs. def_wils, def_sder, def_wlap, app_wils) and its adjoint
 * ``brillouin``  W links (Tab. off-axis) and D_B (Eqs. def_bril, def_ider, def_blap, app_bril)
 * ``staggered``  D_S (Eq. def_stag) and its adjoint
+* ``clover``     clover-leaf field strength and the clover term C (Sec. 4, Eq. def_clov)
+* ``laplace``    the embedded Wilson and Brillouin Laplacians -Delta/2 + m^2/2 (Eqs. app_wlap, app_blap)
 * ``dense``      brute-force dense matrices assembled from the operator-level definitions
 * ``solvers``    CG / BiCGstab (Sec. 9) and the CG-Lanczos spectrum estimate
 * ``force``      link gradients ("fermion force") of Dirac bilinears and solves
