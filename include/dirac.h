@@ -51,7 +51,15 @@ extern "C" {
 #define DIRAC_EWORKSPACE (-4)   /* solver workspace too small */
 #define DIRAC_ENONFINITE (-5)   /* non-finite norm of b or of a residual */
 
-typedef enum { DIRAC_WILSON = 0, DIRAC_BRILLOUIN = 1, DIRAC_STAGGERED = 2 } dirac_op;
+/* Operators.  The two Laplace operators are the spin-trivial "embedded" Laplacians of Secs. 5 and 6,
+ * acting on Wilson-layout vectors; they are hermitian (D^dagger = D). */
+typedef enum {
+    DIRAC_WILSON = 0,
+    DIRAC_BRILLOUIN = 1,
+    DIRAC_STAGGERED = 2,
+    DIRAC_WILSON_LAPLACE = 3,    /* -1/2 Delta^std + m^2/2 (Eq. app_wlap), gauge U */
+    DIRAC_BRILLOUIN_LAPLACE = 4  /* -1/2 Delta^bri + m^2/2 (Eq. app_blap), gauge W */
+} dirac_op;
 
 /* Storage precision of the vectors.  FP64: complex128 vectors and complex128
  * gauge/links.  FP32: complex64 vectors and links.  BF16: bfloat16-pair vectors
@@ -75,7 +83,12 @@ typedef struct {
  * Staggered (Sec. 7, Eq. def_stag):
  *   (D_S u)(n) = m u(n) + 1/2 sum_mu eta_mu(n) [U_mu(n) u(n+mu) - U_mu(n-mu)^+ u(n-mu)],
  *   eta_mu(n) = (-1)^(x_0 + ... + x_{mu-1}) on 0-based coordinates.
- * gauge: U (Wilson, staggered) or W (Brillouin) in the gauge precision of `prec`.
+ * Wilson Laplacian (Sec. 5, Eq. app_wlap; colour only, every spin component alike):
+ *   (4 + m^2/2) u(n) - 1/2 sum_mu [U_mu(n) u(n+mu) + U_mu(n-mu)^+ u(n-mu)]
+ * Brillouin Laplacian (Sec. 6, Eq. app_blap):
+ *   (m^2/2 - lambda_0/2) u(n) - sum_{d != 0} (lambda_|d|/2) W_d(n) u(n+d)
+ * gauge: U (Wilson, staggered, Wilson Laplacian) or W (Brillouin, Brillouin Laplacian) in the gauge
+ * precision of `prec`.  Vectors: staggered layout for DIRAC_STAGGERED, Wilson layout for the others.
  * u, v : vectors in the layout of `op`; u and v must not overlap.
  * Errors: EINVAL (nulls, u == v, bad extents, nv out of range), EUNSUPPORTED (nc), EHIP.
  */
@@ -83,14 +96,39 @@ int dirac_apply(dirac_op op, dirac_prec prec, const void* gauge, const void* u, 
                 int nv, const dirac_dims* dims, void* stream);
 
 /* v = D^dagger u: gamma_5 D gamma_5 for Wilson and Brillouin (Sec. 9: D is gamma_5-hermitian),
- * m - (hopping part) for staggered.  Same arguments and errors as dirac_apply. */
+ * m - (hopping part) for staggered, D itself for the (hermitian) Laplacians.  Same arguments and
+ * errors as dirac_apply. */
 int dirac_apply_dagger(dirac_op op, dirac_prec prec, const void* gauge, const void* u, void* v, double mass,
                        int nc, int nv, const dirac_dims* dims, void* stream);
 
 /* v = D^dagger D u through the caller's scratch vector tmp (App. F: the normal
- * operators of the CG solvers).  u, v, tmp pairwise distinct. */
+ * operators of the CG solvers).  u, v, tmp pairwise distinct.  For the Laplacians (hermitian
+ * positive definite, solved by CG directly) v = D u and tmp is not touched. */
 int dirac_apply_normal(dirac_op op, dirac_prec prec, const void* gauge, const void* u, void* v, void* tmp,
                        double mass, int nc, int nv, const dirac_dims* dims, void* stream);
+
+/*
+ * Clover term (Sec. 4, Eq. def_clov): C(n) = -(c_SW/2) sum_{mu<nu} sigma_{mu nu} F_{mu nu}(n), sigma of
+ * App. A, F_{mu nu}(n) the clover-leaf field strength (Q - Q^+)/(8i) with its trace removed, Q the sum of
+ * the four plaquettes of the (mu, nu) plane that start and end at n.
+ * dirac_clover_field builds the site-diagonal C once per gauge field: in the chiral basis C is two
+ * hermitian 2Nc x 2Nc blocks per site (spins 0,1 and spins 2,3), stored packed as reals: per site block 0
+ * then block 1, each the 2Nc diagonal entries followed by the entries (i, j), i < j, row by row as
+ * (re, im); component i of a block is spin 2h + i/Nc, colour i%Nc.  c_SW is folded in.
+ *   prec FP64: U complex128, clover doubles; FP32 or BF16: U complex64, clover floats.
+ *   clover holds dirac_clover_field_bytes(prec, nc, dims) bytes (8 Nc^2 reals per site); it must not
+ *   overlap U.  Errors: EINVAL, EUNSUPPORTED (nc), EHIP.
+ * dirac_apply_clover / dirac_apply_clover_dagger: v = (D + C) u and v = (D + C)^dagger u = D^dagger u + C u
+ *   (C is hermitian) for op DIRAC_WILSON or DIRAC_BRILLOUIN (Eqs. def_wils, def_bril with c_SW > 0);
+ *   otherwise as dirac_apply.  clover comes from dirac_clover_field in the precision of `prec`.
+ */
+size_t dirac_clover_field_bytes(dirac_prec prec, int nc, const dirac_dims* dims);
+int dirac_clover_field(dirac_prec prec, const void* U, double csw, void* clover, int nc, const dirac_dims* dims,
+                       void* stream);
+int dirac_apply_clover(dirac_op op, dirac_prec prec, const void* gauge, const void* clover, const void* u, void* v,
+                       double mass, int nc, int nv, const dirac_dims* dims, void* stream);
+int dirac_apply_clover_dagger(dirac_op op, dirac_prec prec, const void* gauge, const void* clover, const void* u,
+                              void* v, double mass, int nc, int nv, const dirac_dims* dims, void* stream);
 
 /*
  * Brillouin links (Sec. 6, Tab. off-axis): W_d(n) = average over all |d|! orderings of the
@@ -153,8 +191,11 @@ int dirac_gamma5(dirac_op op, dirac_prec prec, const void* x, void* y, int nc, i
 
 /*
  * Solvers (Sec. 9).  N_v independent solves in lock-step.
- *   cg_solve      : D^dagger D x = b   (conjugate gradients on the hermitian positive normal operator)
+ *   cg_solve      : D^dagger D x = b   (conjugate gradients on the hermitian positive normal operator;
+ *                                       for the two Laplacians, which are hermitian positive definite,
+ *                                       D x = b directly)
  *   bicgstab_solve: D x = b            (BiCGstab; Wilson and Brillouin)
+ * With opts->clover_hi (and clover_lo for a mixed solve) D is D + C (Wilson, Brillouin).
  * outer: precision of b and x (FP64 or FP32).  inner == outer: plain solve.  inner lower
  * than outer (FP32 or BF16 under an FP64 outer): mixed precision -- the true residual,
  * the solution update and all dot products stay in FP64 on the GPU while the operator
@@ -189,6 +230,8 @@ typedef struct {
     double delta;         /* reliable-update factor (0: default 0.1); with defect correction the inner
                            * solves' relative tolerance (0: default 1e-5 FP32, 5e-2 BF16) */
     int max_outer;        /* defect-correction cycles; 0: default 100 */
+    const void* clover_hi; /* clover field in the outer precision (dirac_clover_field) or NULL: no clover */
+    const void* clover_lo; /* clover field in the inner precision (floats), needed by mixed solves with clover_hi */
 } dirac_solve_opts;
 
 size_t dirac_solver_workspace_bytes(dirac_op op, int solver /* 0 = CG on D^+D, 1 = BiCGstab on D */,
@@ -203,21 +246,15 @@ int bicgstab_solve(dirac_op op, dirac_prec outer, dirac_prec inner, const void* 
                    int maxit, void* workspace, size_t ws_bytes, dirac_solve_info* info,
                    const dirac_solve_opts* opts, void* stream);
 
-/* Launch-shape knob for the stencil kernels of (op, prec): rb = right-hand sides handled by
- * one thread (0 automatic; 1, 2 or 4, Brillouin 1 or 2; used whenever it divides nv);
- * variant = 0 automatic, 1 direct global loads (hops unrolled), 2 LDS-staged site tiles,
- * 3 direct global loads with one hop direction per loop iteration (Wilson, staggered),
- * 4 row tiles (Wilson: a work-group stages one x-row of the lattice in LDS with contiguous
- * loads, the next hop direction in flight while the current one is consumed; rows taken in
- * 4 x 4 (y, z) blocks with t next; the RHS stride is a compile-time constant when nv = 12),
- * 5 the same with a runtime RHS stride, 6 the same in 8 x 8 (y, z) blocks, 7 t slabs (one per XCD) of
- * 4 x 4 blocks, 8 as 4 with each direction's links staged in LDS beside the row copy (nv = 12,
- * 1 RHS per thread; otherwise as 5).  Brillouin: 4 row tiles (a work-group walks the 27
- * neighbouring x-rows of its row, each staged in LDS with a window of three links per site),
- * anything else direct global loads.  Staggered: 4 row tiles as for Wilson (one x-row per
- * work-group, the six other neighbour rows staged in turn), 8 the same with each direction's links
- * staged in LDS (at most two link entries per thread, else as 4), anything else direct loads.
- * Results agree to rounding whatever the shape.  Process-wide, not thread-safe. */
+/* Launch-shape knob for the stencil kernels of (op, prec): rb = right-hand-side columns handled by
+ * one thread (0 automatic; Wilson 1 or 2, staggered and Wilson Laplacian 1, 2 or 4, Brillouin and
+ * Brillouin Laplacian 1; used whenever it divides the columns; the Wilson Laplacian sees 4 Nv columns);
+ * variant = 0 automatic, 1 direct global loads (one thread per site and rb columns), 4 row tiles
+ * (a work-group stages one x-row of the lattice and its neighbour rows in LDS with contiguous loads,
+ * the next row in flight while the current one is consumed; Wilson with Nv = 12 and staggered in
+ * FP32/BF16 also stage each direction's links in LDS; the Brillouin kernels walk the 27 neighbouring
+ * x-rows with a window of three links per site).  Row tiles fall back to direct loads for shapes they
+ * cannot take.  Results agree to rounding whatever the shape.  Process-wide, not thread-safe. */
 int dirac_set_launch_shape(dirac_op op, dirac_prec prec, int rb, int variant);
 
 /* Measurement probes (not part of the method): the device's sustained rates, the measured

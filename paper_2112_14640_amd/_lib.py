@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdirac.so
 
 OK, NOT_CONVERGED, EINVAL, EUNSUPPORTED, EHIP, EWORKSPACE, ENONFINITE = 0, 1, -1, -2, -3, -4, -5
 
-WILSON, BRILLOUIN, STAGGERED = 0, 1, 2
+WILSON, BRILLOUIN, STAGGERED, WILSON_LAPLACE, BRILLOUIN_LAPLACE = 0, 1, 2, 3, 4
 FP64, FP32, BF16 = 0, 1, 2
 
 
@@ -41,6 +41,8 @@ class SolveOpts(C.Structure):
         ("mixed_scheme", C.c_int),
         ("delta", C.c_double),
         ("max_outer", C.c_int),
+        ("clover_hi", C.c_void_p),
+        ("clover_lo", C.c_void_p),
     ]
 
 
@@ -55,6 +57,10 @@ SIGNATURES = {
     "dirac_apply": (_i, [_i, _i, _vp, _vp, _vp, _d, _i, _i, _dims, _vp]),
     "dirac_apply_dagger": (_i, [_i, _i, _vp, _vp, _vp, _d, _i, _i, _dims, _vp]),
     "dirac_apply_normal": (_i, [_i, _i, _vp, _vp, _vp, _vp, _d, _i, _i, _dims, _vp]),
+    "dirac_apply_clover": (_i, [_i, _i, _vp, _vp, _vp, _vp, _d, _i, _i, _dims, _vp]),
+    "dirac_apply_clover_dagger": (_i, [_i, _i, _vp, _vp, _vp, _vp, _d, _i, _i, _dims, _vp]),
+    "dirac_clover_field_bytes": (_sz, [_i, _i, _dims]),
+    "dirac_clover_field": (_i, [_i, _vp, _d, _vp, _i, _dims, _vp]),
     "dirac_brillouin_links": (_i, [_i, _vp, _vp, _i, _dims, _vp]),
     "dirac_force": (_i, [_i, _vp, _vp, _vp, _vp, _d, _i, _i, _dims, _vp]),
     "dirac_project_su": (_i, [_vp, _vp, _vp, _i, _i64, _vp]),

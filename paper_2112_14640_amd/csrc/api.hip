@@ -22,11 +22,12 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb) {
 bool aligned(const void* p, size_t a) { return reinterpret_cast<uintptr_t>(p) % a == 0; }
 
 // Launch-shape overrides, [op][prec]; 0 = automatic.
-int g_rb_override[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-int g_variant_override[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+constexpr int kOps = 5;
+int g_rb_override[kOps][3] = {};
+int g_variant_override[kOps][3] = {};
 
 int check_common(dirac_op op, dirac_prec prec, int nc, int nv, const dirac_dims* dims, Geom& g) {
-    if (op < DIRAC_WILSON || op > DIRAC_STAGGERED) return fail(DIRAC_EINVAL, "unknown operator");
+    if (op < DIRAC_WILSON || op > DIRAC_BRILLOUIN_LAPLACE) return fail(DIRAC_EINVAL, "unknown operator");
     if (prec < DIRAC_FP64 || prec > DIRAC_BF16) return fail(DIRAC_EINVAL, "unknown precision");
     if (!dims) return fail(DIRAC_EINVAL, "dims is NULL");
     for (int mu = 0; mu < 4; ++mu) {
@@ -45,15 +46,19 @@ int check_common(dirac_op op, dirac_prec prec, int nc, int nv, const dirac_dims*
     return DIRAC_OK;
 }
 
-int64_t rows_of(dirac_op op, int nc, const Geom& g) { return g.vol * nc * (op == DIRAC_STAGGERED ? 1 : 4); }
+int64_t rows_of(dirac_op op, int nc, const Geom& g) { return g.vol * nc * (op_four_spin(op) ? 4 : 1); }
 
 size_t gauge_bytes(dirac_op op, dirac_prec prec, int nc, const Geom& g) {
-    const int dirs = op == DIRAC_BRILLOUIN ? 40 : 4;
+    const int dirs = op_uses_w(op) ? 40 : 4;
     return static_cast<size_t>(g.vol) * dirs * nc * nc * gauge_complex_bytes(prec);
 }
 
-int stencil(dirac_op op, dirac_prec prec, const void* gauge, const void* u, void* v, double mass, int nc, int nv,
-            const dirac_dims* dims, void* stream, bool dag) {
+size_t clover_bytes(dirac_prec prec, int nc, const Geom& g) {
+    return static_cast<size_t>(g.vol) * clover_field_reals(nc) * (prec == DIRAC_FP64 ? 8 : 4);
+}
+
+int stencil(dirac_op op, dirac_prec prec, const void* gauge, const void* clover, const void* u, void* v, double mass,
+            int nc, int nv, const dirac_dims* dims, void* stream, bool dag) {
     Geom g;
     int rc = check_common(op, prec, nc, nv, dims, g);
     if (rc) return rc;
@@ -64,14 +69,13 @@ int stencil(dirac_op op, dirac_prec prec, const void* gauge, const void* u, void
     if (!aligned(u, complex_bytes(prec)) || !aligned(v, complex_bytes(prec)) ||
         !aligned(gauge, gauge_complex_bytes(prec)))
         return fail(DIRAC_EINVAL, "misaligned pointer");
-    if (!std::isfinite(mass)) return fail(DIRAC_EINVAL, "mass is not finite");
-    StencilArgs a{prec, nc, nv, choose_rb(op, prec, nc, nv), choose_variant(op, prec), dag, mass, g, gauge, u, v};
-    hipStream_t st = as_stream(stream);
-    switch (op) {
-        case DIRAC_WILSON: rc = launch_wilson(a, st); break;
-        case DIRAC_BRILLOUIN: rc = launch_brillouin(a, st); break;
-        case DIRAC_STAGGERED: rc = launch_staggered(a, st); break;
+    if (clover) {
+        if (!op_takes_clover(op)) return fail(DIRAC_EINVAL, "the clover term belongs to Wilson and Brillouin");
+        if (!aligned(clover, prec == DIRAC_FP64 ? 8 : 4)) return fail(DIRAC_EINVAL, "misaligned clover field");
+        if (overlap(clover, clover_bytes(prec, nc, g), v, vb)) return fail(DIRAC_EINVAL, "clover and output overlap");
     }
+    if (!std::isfinite(mass)) return fail(DIRAC_EINVAL, "mass is not finite");
+    rc = launch_stencil(op, prec, nc, nv, g, mass, gauge, clover, u, v, dag, as_stream(stream));
     if (rc) return fail(rc, "stencil launch rejected");
     DIRAC_HIP(hipGetLastError());
     return DIRAC_OK;
@@ -91,50 +95,67 @@ int check_hip(hipError_t e, const char* what) {
     return DIRAC_EHIP;
 }
 
-// Default launch shapes, chosen by timing every shape at 16^3 x 32 and 32^3 x 64, Nc = 3,
-// Nv = 12 on MI355X:
-//   Wilson: row tiles (one x-row per work-group staged in LDS), 1 RHS per thread, each
-//           direction's links staged in LDS beside the row and the RHS stride fixed for Nv = 12
-//           (variant 8; other Nv run as variant 5).  Shapes the row tiles cannot take fall back to
-//           direct loads with one hop per iteration.
-//   staggered: row tiles, 2 RHS/thread, FP32 and BF16 with each direction's links staged in LDS
-//              (variant 8), FP64 with per-thread link loads (variant 4: the staged form touches
-//              scratch in FP64); direct loads with the hops unrolled where a row does not fit
-//   Brillouin: 1 RHS/thread; FP32 and BF16 row tiles (27 row copies per x-row, link windows in
-//              LDS), FP64 direct loads (the row tile spills registers in FP64)
-// A shape that does not divide nv falls back to fewer RHS per thread.
-int choose_rb(dirac_op op, dirac_prec prec, int nc, int nv) {
-    const int o = g_rb_override[op][prec];
-    if (o > 0 && nv % o == 0) return o;
+// Default launch shapes, chosen by timing the shapes at 16^3 x 32 and 32^3 x 64, Nc = 3, Nv = 12 on
+// MI355X:
+//   Wilson: row tiles (one x-row per work-group staged in LDS), 1 RHS per thread (2 where a row of
+//           single-RHS threads would exceed 512 threads); with Nv = 12 each direction's links are
+//           staged in LDS beside the row and the RHS stride is a compile-time constant.
+//   staggered: row tiles, 2 RHS per thread (4 where 2 would exceed 512 threads per row); FP32 and
+//              BF16 stage each direction's links in LDS, FP64 loads them per thread.
+//   Wilson Laplacian: the staggered row kernel on 4 Nv columns, 4 per thread.
+//   Brillouin (and its Laplacian): 1 RHS per thread; FP32 and BF16 row tiles (27 row copies per
+//              x-row, link windows in LDS), FP64 direct loads (the row tile spills registers in FP64).
+// Row tiles fall back to direct loads for shapes they cannot take; an rb that does not divide the
+// columns falls back to 1.
+int choose_rb(dirac_op op, dirac_prec prec, int nc, int nv, const Geom& g) {
     (void)nc;
-    (void)prec;
+    const int cols = op == DIRAC_WILSON_LAPLACE ? 4 * nv : nv;
+    const int o = g_rb_override[op][prec];
+    if (o > 0) return cols % o == 0 ? o : 1;
     switch (op) {
         case DIRAC_WILSON:
-            return 1;
-        case DIRAC_STAGGERED:
-            return nv % 2 == 0 ? 2 : 1;  // row tiles with 2 RHS per thread
-        case DIRAC_BRILLOUIN:
+            return (static_cast<int64_t>(g.nx) * nv > 512 && nv % 2 == 0) ? 2 : 1;
+        case DIRAC_STAGGERED: {
+            if (cols % 2 != 0) return 1;
+            return (static_cast<int64_t>(g.nx) * cols / 2 > 512 && cols % 4 == 0) ? 4 : 2;
+        }
+        case DIRAC_WILSON_LAPLACE:
+            return 4;
+        default:
             return 1;
     }
-    return 1;
 }
 
-// 1 = direct loads with hops unrolled, 2 = LDS-staged site tiles, 3 = direct loads, one hop per
-// iteration, 4..7 = row tiles (Wilson; see dirac_set_launch_shape)
+// 1 = direct loads, 4 = row tiles (see dirac_set_launch_shape)
 int choose_variant(dirac_op op, dirac_prec prec) {
     const int o = g_variant_override[op][prec];
     if (o > 0) return o;
-    if (op == DIRAC_WILSON) return 8;
-    if (op == DIRAC_BRILLOUIN) return prec == DIRAC_FP64 ? 1 : 4;
-    return prec == DIRAC_FP64 ? 4 : 8;  // staggered
+    if (op_uses_w(op)) return prec == DIRAC_FP64 ? 1 : 4;
+    return 4;
+}
+
+int launch_stencil(dirac_op op, dirac_prec prec, int nc, int nv, const Geom& g, double mass, const void* gauge,
+                   const void* clover, const void* in, void* out, bool dag, hipStream_t st) {
+    StencilArgs a{prec, nc, nv, choose_rb(op, prec, nc, nv, g), choose_variant(op, prec), dag, mass, g, gauge, in, out};
+    a.clover = op_takes_clover(op) ? clover : nullptr;
+    a.laplace = op_is_laplace(op);
+    if (a.laplace) a.dagger = false;  // hermitian
+    switch (op) {
+        case DIRAC_WILSON: return launch_wilson(a, st);
+        case DIRAC_BRILLOUIN:
+        case DIRAC_BRILLOUIN_LAPLACE: return launch_brillouin(a, st);
+        case DIRAC_STAGGERED:
+        case DIRAC_WILSON_LAPLACE: return launch_staggered(a, st);
+    }
+    return DIRAC_EINVAL;
 }
 
 size_t solver_workspace_bytes(dirac_op op, int solver, dirac_prec outer, dirac_prec inner, int nc, int nv,
                               const Geom& g, int scheme);
 int run_solver(int solver, dirac_op op, dirac_prec outer, dirac_prec inner, const void* gauge_hi,
-               const void* gauge_lo, const void* b, void* x, double mass, int nc, int nv, const Geom& g, double tol,
-               int maxit, void* workspace, size_t ws_bytes, dirac_solve_info* info, const dirac_solve_opts* opts,
-               hipStream_t st);
+               const void* gauge_lo, const void* clov_hi, const void* clov_lo, const void* b, void* x, double mass,
+               int nc, int nv, const Geom& g, double tol, int maxit, void* workspace, size_t ws_bytes,
+               dirac_solve_info* info, const dirac_solve_opts* opts, hipStream_t st);
 
 }  // namespace dirac
 
@@ -144,12 +165,47 @@ extern "C" {
 
 int dirac_apply(dirac_op op, dirac_prec prec, const void* gauge, const void* u, void* v, double mass, int nc, int nv,
                 const dirac_dims* dims, void* stream) {
-    return stencil(op, prec, gauge, u, v, mass, nc, nv, dims, stream, false);
+    return stencil(op, prec, gauge, nullptr, u, v, mass, nc, nv, dims, stream, false);
 }
 
 int dirac_apply_dagger(dirac_op op, dirac_prec prec, const void* gauge, const void* u, void* v, double mass, int nc,
                        int nv, const dirac_dims* dims, void* stream) {
-    return stencil(op, prec, gauge, u, v, mass, nc, nv, dims, stream, true);
+    return stencil(op, prec, gauge, nullptr, u, v, mass, nc, nv, dims, stream, true);
+}
+
+int dirac_apply_clover(dirac_op op, dirac_prec prec, const void* gauge, const void* clover, const void* u, void* v,
+                       double mass, int nc, int nv, const dirac_dims* dims, void* stream) {
+    if (!clover) return fail(DIRAC_EINVAL, "NULL clover field");
+    return stencil(op, prec, gauge, clover, u, v, mass, nc, nv, dims, stream, false);
+}
+
+int dirac_apply_clover_dagger(dirac_op op, dirac_prec prec, const void* gauge, const void* clover, const void* u,
+                              void* v, double mass, int nc, int nv, const dirac_dims* dims, void* stream) {
+    if (!clover) return fail(DIRAC_EINVAL, "NULL clover field");
+    return stencil(op, prec, gauge, clover, u, v, mass, nc, nv, dims, stream, true);
+}
+
+size_t dirac_clover_field_bytes(dirac_prec prec, int nc, const dirac_dims* dims) {
+    Geom g;
+    if (check_common(DIRAC_WILSON, prec, nc, 1, dims, g)) return 0;
+    return clover_bytes(prec, nc, g);
+}
+
+int dirac_clover_field(dirac_prec prec, const void* U, double csw, void* clover, int nc, const dirac_dims* dims,
+                       void* stream) {
+    Geom g;
+    int rc = check_common(DIRAC_WILSON, prec, nc, 1, dims, g);
+    if (rc) return rc;
+    if (!U || !clover) return fail(DIRAC_EINVAL, "NULL pointer");
+    if (!std::isfinite(csw)) return fail(DIRAC_EINVAL, "c_SW is not finite");
+    if (!aligned(U, gauge_complex_bytes(prec)) || !aligned(clover, prec == DIRAC_FP64 ? 8 : 4))
+        return fail(DIRAC_EINVAL, "misaligned pointer");
+    if (overlap(U, gauge_bytes(DIRAC_WILSON, prec, nc, g), clover, clover_bytes(prec, nc, g)))
+        return fail(DIRAC_EINVAL, "U and the clover field overlap");
+    rc = launch_clover_field(prec, nc, g, U, clover, csw, as_stream(stream));
+    if (rc) return fail(rc, "clover launch rejected");
+    DIRAC_HIP(hipGetLastError());
+    return DIRAC_OK;
 }
 
 int dirac_apply_normal(dirac_op op, dirac_prec prec, const void* gauge, const void* u, void* v, void* tmp,
@@ -161,9 +217,10 @@ int dirac_apply_normal(dirac_op op, dirac_prec prec, const void* gauge, const vo
     const size_t vb = static_cast<size_t>(rows_of(op, nc, g)) * nv * complex_bytes(prec);
     if (u && (overlap(u, vb, tmp, vb) || (v && overlap(v, vb, tmp, vb))))
         return fail(DIRAC_EINVAL, "scratch vector overlaps input or output");
-    rc = stencil(op, prec, gauge, u, tmp, mass, nc, nv, dims, stream, false);
+    if (op_is_laplace(op)) return stencil(op, prec, gauge, nullptr, u, v, mass, nc, nv, dims, stream, false);
+    rc = stencil(op, prec, gauge, nullptr, u, tmp, mass, nc, nv, dims, stream, false);
     if (rc) return rc;
-    return stencil(op, prec, gauge, tmp, v, mass, nc, nv, dims, stream, true);
+    return stencil(op, prec, gauge, nullptr, tmp, v, mass, nc, nv, dims, stream, true);
 }
 
 int dirac_brillouin_links(dirac_prec prec, const void* U, void* W, int nc, const dirac_dims* dims, void* stream) {
@@ -186,7 +243,8 @@ int dirac_force(dirac_op op, const void* U, const void* psi, const void* chi, vo
     Geom g;
     int rc = check_common(op, DIRAC_FP64, nc, nv, dims, g);
     if (rc) return rc;
-    if (op == DIRAC_BRILLOUIN) return fail(DIRAC_EUNSUPPORTED, "force is implemented for Wilson and staggered");
+    if (op != DIRAC_WILSON && op != DIRAC_STAGGERED)
+        return fail(DIRAC_EUNSUPPORTED, "force is implemented for Wilson and staggered");
     if (!psi || !chi || !gout) return fail(DIRAC_EINVAL, "NULL pointer");
     const size_t vb = static_cast<size_t>(rows_of(op, nc, g)) * nv * 16;
     const size_t gb = gauge_bytes(op, DIRAC_FP64, nc, g);
@@ -323,8 +381,17 @@ static int solve(int solver, dirac_op op, dirac_prec outer, dirac_prec inner, co
     const bool mixed = inner != outer;
     if (mixed && (outer != DIRAC_FP64 || inner == DIRAC_FP64))
         return fail(DIRAC_EUNSUPPORTED, "mixed precision needs an FP64 outer and an FP32/BF16 inner precision");
-    if (solver == 1 && op == DIRAC_STAGGERED) return fail(DIRAC_EUNSUPPORTED, "BiCGstab is for Wilson and Brillouin");
+    if (solver == 1 && op != DIRAC_WILSON && op != DIRAC_BRILLOUIN)
+        return fail(DIRAC_EUNSUPPORTED, "BiCGstab is for Wilson and Brillouin");
     if (!gauge_hi || !b || !x || !workspace || (mixed && !gauge_lo)) return fail(DIRAC_EINVAL, "NULL pointer");
+    const void* clov_hi = opts ? opts->clover_hi : nullptr;
+    const void* clov_lo = opts ? opts->clover_lo : nullptr;
+    if (clov_hi) {
+        if (!op_takes_clover(op)) return fail(DIRAC_EINVAL, "the clover term belongs to Wilson and Brillouin");
+        if (mixed && !clov_lo) return fail(DIRAC_EINVAL, "a mixed solve with a clover field needs clover_lo");
+        if (!aligned(clov_hi, outer == DIRAC_FP64 ? 8 : 4) || (mixed && !aligned(clov_lo, 4)))
+            return fail(DIRAC_EINVAL, "misaligned clover field");
+    }
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(DIRAC_EINVAL, "tolerance must be positive");
     if (maxit < 0) return fail(DIRAC_EINVAL, "maxit must be >= 0");
     if (!std::isfinite(mass)) return fail(DIRAC_EINVAL, "mass is not finite");
@@ -336,8 +403,8 @@ static int solve(int solver, dirac_op op, dirac_prec outer, dirac_prec inner, co
         info->iters = info->outer_iters = info->reason = 0;
         info->hist_len = 0;
     }
-    return run_solver(solver, op, outer, inner, gauge_hi, gauge_lo, b, x, mass, nc, nv, g, tol, maxit, workspace,
-                      ws_bytes, info, opts, as_stream(stream));
+    return run_solver(solver, op, outer, inner, gauge_hi, gauge_lo, clov_hi, mixed ? clov_lo : nullptr, b, x, mass,
+                      nc, nv, g, tol, maxit, workspace, ws_bytes, info, opts, as_stream(stream));
 }
 
 int cg_solve(dirac_op op, dirac_prec outer, dirac_prec inner, const void* gauge_hi, const void* gauge_lo,
@@ -356,12 +423,12 @@ int bicgstab_solve(dirac_op op, dirac_prec outer, dirac_prec inner, const void* 
 }
 
 int dirac_set_launch_shape(dirac_op op, dirac_prec prec, int rb, int variant) {
-    if (op < DIRAC_WILSON || op > DIRAC_STAGGERED || prec < DIRAC_FP64 || prec > DIRAC_BF16)
+    if (op < DIRAC_WILSON || op > DIRAC_BRILLOUIN_LAPLACE || prec < DIRAC_FP64 || prec > DIRAC_BF16)
         return fail(DIRAC_EINVAL, "unknown operator or precision");
-    const int maxrb = op == DIRAC_BRILLOUIN ? 2 : 4;
+    const int maxrb = op_uses_w(op) ? 1 : (op == DIRAC_WILSON ? 2 : 4);
     if (rb != 0 && rb != 1 && rb != 2 && rb != 4) return fail(DIRAC_EINVAL, "rb must be 0, 1, 2 or 4");
     if (rb > maxrb) return fail(DIRAC_EUNSUPPORTED, "rb not instantiated for this operator");
-    if (variant < 0 || variant > 8) return fail(DIRAC_EINVAL, "variant must be 0..8");
+    if (variant != 0 && variant != 1 && variant != 4) return fail(DIRAC_EINVAL, "variant must be 0, 1 or 4");
     g_rb_override[op][prec] = rb;
     g_variant_override[op][prec] = variant;
     return DIRAC_OK;
@@ -373,6 +440,8 @@ double dirac_flops_per_site(dirac_op op, int nc) {
         case DIRAC_WILSON: return 128.0 * n * n + 72.0 * n;
         case DIRAC_BRILLOUIN: return 2560.0 * n * n + 2376.0 * n;
         case DIRAC_STAGGERED: return 64.0 * n * n + 2.0 * n;
+        case DIRAC_WILSON_LAPLACE: return 256.0 * n * n + 8.0 * n;
+        case DIRAC_BRILLOUIN_LAPLACE: return 2560.0 * n * n + 648.0 * n;
     }
     return 0.0;
 }

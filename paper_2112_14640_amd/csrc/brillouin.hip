@@ -12,9 +12,14 @@
 // which is Eq. app_bril with the derivative factor of Eq. def_ider written out; the adjoint
 // negates the rho part (g_5-hermiticity).  In the chiral basis sum_mu c_mu g_mu is
 // [[0, B], [B^+, 0]] with B = [[c4 - i c3, -c2 - i c1], [c2 - i c1, c4 + i c3]] (App. C).
+// The optional clover term C of Eq. def_clov is added at the centre (hermitian: the adjoint adds it
+// unchanged).  With the flag lap the same kernels apply the Brillouin Laplacian of Eq. app_blap,
+//   (-1/2 Delta^bri + m^2/2) u(n) = (m^2/2 - lambda_0/2) u(n) - sum_{d != 0} (lambda_|d|/2) W_d(n) u(n+d),
+// the spin-trivial part of the stencil (the rho terms are skipped; the caller passes the diagonal).
 #include <mutex>
 #include <type_traits>
 
+#include "clover.h"
 #include "common.h"
 #include "kernels.h"
 #include "tile.h"
@@ -177,7 +182,8 @@ template <int NC, int RB, bool DAG, class P>
 __global__ __launch_bounds__(256) void brillouin_kernel(const typename P::G* __restrict__ W,
                                                          const typename P::S* __restrict__ in,
                                                          typename P::S* __restrict__ out, typename P::R diag, Geom g,
-                                                         int nv, SiteOrder order) {
+                                                         int nv, SiteOrder order, const typename P::R* __restrict__ clov,
+                                                         int lap) {
     using R = typename P::R;
     using S = typename P::S;
     const int nrg = nv / RB;
@@ -197,6 +203,7 @@ __global__ __launch_bounds__(256) void brillouin_kernel(const typename P::G* __r
         for (int a = 0; a < NC; ++a)
 #pragma unroll
             for (int s = 0; s < 4; ++s) acc[k][a][s] = cscale(diag, io<R, S>::ld(centre + (a * 4 + s) * nv + k));
+    if (clov) clover_add<NC, RB>(acc, centre, nv, clov + site * clover_reals<NC>());
 
     // neighbour offsets along each axis for steps -1, 0, +1 (with the periodic wrap) and the
     // fermion sign of the t steps; per direction the neighbour is site + four offsets
@@ -249,7 +256,8 @@ __global__ __launch_bounds__(256) void brillouin_kernel(const typename P::G* __r
                 for (int b = 0; b < NC; ++b)
 #pragma unroll
                     for (int s = 0; s < 4; ++s) cfma(ch[s], l[a][b], p[b][s]);
-                spin_accumulate(acc[k][a], ch, lh, q1, q2, q3, q4, ix != 1, iy != 1, iz != 1, it != 1);
+                spin_accumulate(acc[k][a], ch, lh, q1, q2, q3, q4, !lap && ix != 1, !lap && iy != 1, !lap && iz != 1,
+                                !lap && it != 1);
             }
         }
     }
@@ -279,7 +287,8 @@ template <int NC, int RB, bool DAG, class P, int NVC, bool SEG>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(typename P::R) == 8 ? 2 : 3))) void brillouin_rows_kernel(const typename P::G* __restrict__ W,
                                                              const typename P::S* __restrict__ in,
                                                              typename P::S* __restrict__ out, typename P::R diag,
-                                                             Geom g, int nv, RowTile rt) {
+                                                             Geom g, int nv, RowTile rt,
+                                                             const typename P::R* __restrict__ clov, int lap) {
     using R = typename P::R;
     using S = typename P::S;
     using G = typename P::G;
@@ -403,7 +412,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
                 // copy site of x + ix - 1
                 const int cn = SEG ? static_cast<int>(j) + ix : wrap(static_cast<int>(j) + ix - 1, g.nx);
                 const S* nbp = at(cn);
-                if (rc == 13 && ix == 1) {  // the centre: (m - lambda_0 / 2) u(n)
+                if (rc == 13 && ix == 1) {  // the centre: (m - lambda_0 / 2) u(n), plus the clover term
 #pragma unroll
                     for (int k = 0; k < RB; ++k)
 #pragma unroll
@@ -414,6 +423,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
                                 acc[k][a][s].re += diag * v.re;
                                 acc[k][a][s].im += diag * v.im;
                             }
+                    if (clov) clover_add<NC, RB>(acc, nbp, nv, clov + (own_start + x) * clover_reals<NC>());
                     continue;
                 }
                 // W_d(n): stored at the own site (rc < 13, or rc = 13 with d_x = -1), else the
@@ -451,7 +461,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
 #pragma unroll
                                 for (int s = 0; s < 4; ++s) cfma(ch[s], l[a][b], p[b][s]);
                         }
-                        spin_accumulate(acc[k][a], ch, lh, q1, q2, q3, q4, ix != 1, iy != 1, iz != 1, it != 1);
+                        spin_accumulate(acc[k][a], ch, lh, q1, q2, q3, q4, !lap && ix != 1, !lap && iy != 1,
+                                        !lap && iz != 1, !lap && it != 1);
                     }
                 }
             }
@@ -503,6 +514,11 @@ bool ensure_spin_table() {
     return true;
 }
 
+// The centre coefficient: m - lambda_0/2 for D_B, m^2/2 - lambda_0/2 for the Laplacian.
+double centre_coefficient(const StencilArgs& a) {
+    return (a.laplace ? 0.5 * a.mass * a.mass : a.mass) + 120.0 / 64.0;
+}
+
 template <int NC, int RB, class P>
 bool launch_rows(const StencilArgs& a, hipStream_t st) {
     using S = typename P::S;
@@ -548,11 +564,15 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
     const int block = (rt.threads + 63) / 64 * 64;
     const dim3 grid(static_cast<unsigned>(grid_blocks_x8(rt.ntiles, 1)));
     using R = typename P::R;
-    const R diag = static_cast<R>(a.mass + 120.0 / 64.0);
+    const R diag = static_cast<R>(centre_coefficient(a));
     auto W = static_cast<const typename P::G*>(a.gauge);
     auto in = static_cast<const S*>(a.in);
     auto out = static_cast<S*>(a.out);
-    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, grid, dim3(block), lds, st, W, in, out, diag, a.g, a.nv, rt); };
+    auto clov = static_cast<const R*>(a.clover);
+    const int lap = a.laplace ? 1 : 0;
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, dim3(block), lds, st, W, in, out, diag, a.g, a.nv, rt, clov, lap);
+    };
     auto pick = [&](auto seg_c) {
         constexpr bool SG = decltype(seg_c)::value;
         if (a.nv == 12 && RB == 1) {
@@ -581,24 +601,23 @@ void launch_rb(const StencilArgs& a, hipStream_t st) {
     const int block = 256;
     const int64_t threads = a.g.vol * (a.nv / RB);
     const dim3 grid(static_cast<unsigned>(grid_blocks_x8(threads, block)));
-    const R diag = static_cast<R>(a.mass + 120.0 / 64.0);
+    const R diag = static_cast<R>(centre_coefficient(a));
     auto W = static_cast<const typename P::G*>(a.gauge);
     auto in = static_cast<const typename P::S*>(a.in);
     auto out = static_cast<typename P::S*>(a.out);
+    auto clov = static_cast<const R*>(a.clover);
+    const int lap = a.laplace ? 1 : 0;
     if (a.dagger)
         hipLaunchKernelGGL((brillouin_kernel<NC, RB, true, P>), grid, dim3(block), 0, st, W, in, out, diag, a.g, a.nv,
-                           make_site_order(a.g));
+                           make_site_order(a.g), clov, lap);
     else
         hipLaunchKernelGGL((brillouin_kernel<NC, RB, false, P>), grid, dim3(block), 0, st, W, in, out, diag, a.g,
-                           a.nv, make_site_order(a.g));
+                           a.nv, make_site_order(a.g), clov, lap);
 }
 
 template <int NC, class P>
 void launch_nc(const StencilArgs& a, hipStream_t st) {
-    switch (a.rb) {
-        case 2: launch_rb<NC, 2, P>(a, st); break;
-        default: launch_rb<NC, 1, P>(a, st); break;
-    }
+    launch_rb<NC, 1, P>(a, st);
 }
 
 template <class P>

@@ -9,14 +9,16 @@ struct StencilArgs {
     dirac_prec prec;
     int nc;
     int nv;
-    int rb;       // right-hand sides per thread (divides nv)
-    int variant;  // 0: automatic (LDS-staged tile when it fits), 1: direct global loads
+    int rb;       // right-hand sides per thread (divides the columns the kernel sees)
+    int variant;  // 1: direct global loads, 4: row tiles staged in LDS (falls back to 1 where a row does not fit)
     bool dagger;
     double mass;
     Geom g;
     const void* gauge;
     const void* in;
     void* out;
+    const void* clover = nullptr;  // packed clover blocks (clover.h) for Wilson / Brillouin, or none
+    bool laplace = false;          // the spin-trivial Laplace operator of the same stencil
 };
 
 // Stencil launches (asynchronous; arguments already validated).
@@ -24,12 +26,26 @@ int launch_wilson(const StencilArgs& a, hipStream_t st);
 int launch_staggered(const StencilArgs& a, hipStream_t st);
 int launch_brillouin(const StencilArgs& a, hipStream_t st);
 int launch_brillouin_links(dirac_prec prec, int nc, const Geom& g, const void* U, void* W, hipStream_t st);
+int launch_clover_field(dirac_prec prec, int nc, const Geom& g, const void* U, void* C, double csw, hipStream_t st);
+size_t clover_field_reals(int nc);
+
+// Operator classes.  The Laplace operators act on Wilson-layout vectors ([colour][spin][rhs]) and are
+// hermitian; they run on the staggered (Wilson Laplacian) and Brillouin (Brillouin Laplacian) kernels.
+inline bool op_is_laplace(dirac_op op) { return op == DIRAC_WILSON_LAPLACE || op == DIRAC_BRILLOUIN_LAPLACE; }
+inline bool op_four_spin(dirac_op op) { return op != DIRAC_STAGGERED; }
+inline bool op_uses_w(dirac_op op) { return op == DIRAC_BRILLOUIN || op == DIRAC_BRILLOUIN_LAPLACE; }
+inline bool op_takes_clover(dirac_op op) { return op == DIRAC_WILSON || op == DIRAC_BRILLOUIN; }
+
+// Launch one apply of `op` (D, D^+ with dag; the Laplacians ignore dag); rb and variant from the defaults
+// or the dirac_set_launch_shape overrides.
+int launch_stencil(dirac_op op, dirac_prec prec, int nc, int nv, const Geom& g, double mass, const void* gauge,
+                   const void* clover, const void* in, void* out, bool dag, hipStream_t st);
 int launch_force(dirac_op op, int nc, int nv, const Geom& g, const void* U, const void* psi, const void* chi,
                  void* gout, double coeff, hipStream_t st);
 int launch_project_su(int nc, int64_t nlinks, const void* U, const void* g, void* F, hipStream_t st);
 
-// RHS-per-thread choice for a stencil (tunable; must divide nv) and kernel variant.
-int choose_rb(dirac_op op, dirac_prec prec, int nc, int nv);
+// RHS-per-thread choice for a stencil (tunable; divides the columns the kernel sees) and kernel variant.
+int choose_rb(dirac_op op, dirac_prec prec, int nc, int nv, const Geom& g);
 int choose_variant(dirac_op op, dirac_prec prec);
 
 // ---------------------------------------------------------------------------

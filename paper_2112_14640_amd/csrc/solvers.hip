@@ -48,36 +48,38 @@ struct OpCtx {
     double mass;
     int64_t nrows;  // rows of nv complex per vector
     size_t ncomplex() const { return static_cast<size_t>(nrows) * nv; }
+    // the Laplacians are hermitian positive definite: CG runs on D itself, not on D^+ D
+    bool hermitian() const { return op_is_laplace(op); }
+};
+
+// The operator's links and (optional) clover field in one precision.
+struct Field {
+    const void* gauge;
+    const void* clov;
 };
 
 size_t vec_bytes(const OpCtx& o, dirac_prec p) { return o.ncomplex() * complex_bytes(p); }
 
-int apply_op(const OpCtx& o, dirac_prec p, const void* gauge, const void* in, void* out, bool dag, hipStream_t st) {
-    StencilArgs a{p, o.nc, o.nv, choose_rb(o.op, p, o.nc, o.nv), choose_variant(o.op, p), dag, o.mass, o.g, gauge, in,
-                  out};
-    switch (o.op) {
-        case DIRAC_WILSON: return launch_wilson(a, st);
-        case DIRAC_BRILLOUIN: return launch_brillouin(a, st);
-        case DIRAC_STAGGERED: return launch_staggered(a, st);
-    }
-    return DIRAC_EINVAL;
+int apply_op(const OpCtx& o, dirac_prec p, const Field& f, const void* in, void* out, bool dag, hipStream_t st) {
+    return launch_stencil(o.op, p, o.nc, o.nv, o.g, o.mass, f.gauge, f.clov, in, out, dag, st);
 }
 
-// out = D^+ D in, via tmp
-int apply_normal(const OpCtx& o, dirac_prec p, const void* gauge, const void* in, void* out, void* tmp,
+// out = A in with A = D^+ D via tmp (A = D for the hermitian Laplacians; tmp unused)
+int apply_normal(const OpCtx& o, dirac_prec p, const Field& f, const void* in, void* out, void* tmp,
                  hipStream_t st) {
-    int rc = apply_op(o, p, gauge, in, tmp, false, st);
+    if (o.hermitian()) return apply_op(o, p, f, in, out, false, st);
+    int rc = apply_op(o, p, f, in, tmp, false, st);
     if (rc) return rc;
-    return apply_op(o, p, gauge, tmp, out, true, st);
+    return apply_op(o, p, f, tmp, out, true, st);
 }
 
 // Device scalar kernels (one thread per RHS).  alpha = rr / p^+ A p with p^+ A p = ||D p||^2
 // (A = D^+ D), one double per RHS.
-__global__ void k_cg_alpha(const double* __restrict__ pq, const double* __restrict__ rr, const double* __restrict__ mask,
-                           double* __restrict__ alpha, int nv) {
+__global__ void k_cg_alpha(const double* __restrict__ pq, int pq_stride, const double* __restrict__ rr,
+                           const double* __restrict__ mask, double* __restrict__ alpha, int nv) {
     const int i = threadIdx.x;
     if (i >= nv) return;
-    const double d = pq[i];
+    const double d = pq[i * pq_stride];
     const bool ok = mask[i] != 0.0 && d > 0.0 && std::isfinite(d);
     alpha[2 * i] = ok ? rr[i] / d : 0.0;
     alpha[2 * i + 1] = 0.0;
@@ -87,11 +89,11 @@ __global__ void k_cg_alpha(const double* __restrict__ pq, const double* __restri
 // the exact minimiser along the stored direction p of the A-norm of the error.  With p stored in a
 // lower precision than r, <r, p> drifts away from ||r||^2 (the deviation is carried forward by beta)
 // and the textbook ||r||^2 / p^+ A p can then overshoot and make the recurrence diverge.
-__global__ void k_cg_alpha_ls(const double* __restrict__ pq, const double* __restrict__ rp,
+__global__ void k_cg_alpha_ls(const double* __restrict__ pq, int pq_stride, const double* __restrict__ rp,
                               const double* __restrict__ mask, double* __restrict__ alpha, int nv) {
     const int i = threadIdx.x;
     if (i >= nv) return;
-    const double d = pq[i];
+    const double d = pq[i * pq_stride];
     const bool ok = mask[i] != 0.0 && d > 0.0 && std::isfinite(d);
     alpha[2 * i] = ok ? rp[2 * i] / d : 0.0;
     alpha[2 * i + 1] = ok ? -rp[2 * i + 1] / d : 0.0;
@@ -193,7 +195,7 @@ bool all_finite(const std::vector<double>& v) {
 }
 
 // r = b - A x using q and t as temporaries (A = D^+ D in precision pp; x in px).
-int residual_normal(const OpCtx& o, dirac_prec pp, const void* gauge, dirac_prec pb, const void* b, dirac_prec px,
+int residual_normal(const OpCtx& o, dirac_prec pp, const Field& f, dirac_prec pb, const void* b, dirac_prec px,
                     const void* x, dirac_prec pr, void* r, void* q, void* t, hipStream_t st) {
     const void* xin = x;
     if (px != pp) {
@@ -201,9 +203,21 @@ int residual_normal(const OpCtx& o, dirac_prec pp, const void* gauge, dirac_prec
         if (rc) return rc;
         xin = q;
     }
-    int rc = apply_normal(o, pp, gauge, xin, q, t, st);
+    int rc = apply_normal(o, pp, f, xin, q, t, st);
     if (rc) return rc;
     return blas_sub(pb, b, pp, q, pr, r, o.ncomplex(), st);
+}
+
+// p^+ A p into s.pq after q = A p (and t = D p): ||t||^2 for A = D^+ D (one vector read instead of two),
+// Re <p, q> for a hermitian A.  Returns the stride of the real values in s.pq.
+int p_a_p(const OpCtx& o, dirac_prec pp, const void* p, const void* q, const void* t, double* partial, double* pq,
+          int& stride, hipStream_t st) {
+    if (o.hermitian()) {
+        stride = 2;
+        return blas_dot(pp, p, pp, q, o.nrows, o.nv, partial, pq, st);
+    }
+    stride = 1;
+    return blas_norm2(pp, t, o.nrows, o.nv, partial, pq, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -218,7 +232,7 @@ struct CGVecs {
     dirac_prec pr;
     void *p, *q, *t;
     dirac_prec pp;
-    const void* gauge;
+    Field f;
 };
 
 int cg_core(const OpCtx& o, const CGVecs& v, const Rules& ru, Scalars& s, hipStream_t st, Result& res,
@@ -237,7 +251,7 @@ int cg_core(const OpCtx& o, const CGVecs& v, const Rules& ru, Scalars& s, hipStr
         goal[i] = ru.tol * bn[i];
     }
     // r = b - A x ; rr
-    if ((rc = residual_normal(o, v.pp, v.gauge, v.pb, v.b, v.px, v.x, v.pr, v.r, v.q, v.t, st))) return rc;
+    if ((rc = residual_normal(o, v.pp, v.f, v.pb, v.b, v.px, v.x, v.pr, v.r, v.q, v.t, st))) return rc;
     if ((rc = blas_norm2(v.pr, v.r, o.nrows, nv, s.partial, s.rr, st))) return rc;
     if ((rc = d2h(h, s.rr, nv, st))) return rc;
     std::vector<double> rr(h, h + nv), active(nv);
@@ -263,10 +277,10 @@ int cg_core(const OpCtx& o, const CGVecs& v, const Rules& ru, Scalars& s, hipStr
             break;
         }
         ++it;
-        if ((rc = apply_normal(o, v.pp, v.gauge, v.p, v.q, v.t, st))) return rc;
-        // p^+ D^+ D p = ||t||^2 with t = D p: one vector read instead of two
-        if ((rc = blas_norm2(v.pp, v.t, o.nrows, nv, s.partial, s.pq, st))) return rc;
-        hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, st, s.pq, s.rr, s.mask, s.alpha, nv);
+        if ((rc = apply_normal(o, v.pp, v.f, v.p, v.q, v.t, st))) return rc;
+        int pstride;
+        if ((rc = p_a_p(o, v.pp, v.p, v.q, v.t, s.partial, s.pq, pstride, st))) return rc;
+        hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, st, s.pq, pstride, s.rr, s.mask, s.alpha, nv);
         if ((rc = fused_r_update(v.pr, v.r, v.pp, v.q, s.alpha, o.nrows, nv, s.partial, s.rr_new, st))) return rc;
         if ((rc = d2h(h, s.rr_new, nv, st))) return rc;
         std::vector<double> rn(h, h + nv);
@@ -290,7 +304,7 @@ int cg_core(const OpCtx& o, const CGVecs& v, const Rules& ru, Scalars& s, hipStr
         }
         // x += alpha p, then the explicit residual
         if ((rc = blas_caxpy(v.pp, v.p, v.px, v.x, s.alpha, o.nrows, nv, st))) return rc;
-        if ((rc = residual_normal(o, v.pp, v.gauge, v.pb, v.b, v.px, v.x, v.pr, v.r, v.q, v.t, st))) return rc;
+        if ((rc = residual_normal(o, v.pp, v.f, v.pb, v.b, v.px, v.x, v.pr, v.r, v.q, v.t, st))) return rc;
         if ((rc = blas_norm2(v.pr, v.r, o.nrows, nv, s.partial, s.rr_new, st))) return rc;
         if ((rc = d2h(h, s.rr_new, nv, st))) return rc;
         std::vector<double> rt(h, h + nv);
@@ -345,8 +359,8 @@ struct RUVecs {
     void *r, *xl;
     void *p, *q, *t;
     dirac_prec pin;
-    const void* g_hi;
-    const void* g_lo;
+    Field f_hi;
+    Field f_lo;
 };
 
 int cg_reliable(const OpCtx& o, const RUVecs& v, const Rules& ru, double delta, Scalars& s, hipStream_t st,
@@ -366,7 +380,7 @@ int cg_reliable(const OpCtx& o, const RUVecs& v, const Rules& ru, double delta, 
     }
     auto true_residual = [&](std::vector<double>& rt) -> int {
         int e;
-        if ((e = apply_normal(o, F64, v.g_hi, v.x, v.r_hi, v.t_hi, st))) return e;
+        if ((e = apply_normal(o, F64, v.f_hi, v.x, v.r_hi, v.t_hi, st))) return e;
         if ((e = blas_bminus(F64, v.b, F64, v.r_hi, o.nrows, nv, st))) return e;
         if ((e = blas_norm2(F64, v.r_hi, o.nrows, nv, s.partial, s.tmpn, st))) return e;
         if ((e = d2h(h, s.tmpn, nv, st))) return e;
@@ -413,9 +427,10 @@ int cg_reliable(const OpCtx& o, const RUVecs& v, const Rules& ru, double delta, 
             break;
         }
         ++it;
-        if ((rc = apply_normal(o, v.pin, v.g_lo, v.p, v.q, v.t, st))) return rc;
-        if ((rc = blas_norm2(v.pin, v.t, o.nrows, nv, s.partial, s.pq, st))) return rc;  // ||D p||^2
-        hipLaunchKernelGGL(k_cg_alpha_ls, dim3(1), dim3(256), 0, st, s.pq, s.rp, s.mask, s.alpha, nv);
+        if ((rc = apply_normal(o, v.pin, v.f_lo, v.p, v.q, v.t, st))) return rc;
+        int pstride;
+        if ((rc = p_a_p(o, v.pin, v.p, v.q, v.t, s.partial, s.pq, pstride, st))) return rc;
+        hipLaunchKernelGGL(k_cg_alpha_ls, dim3(1), dim3(256), 0, st, s.pq, pstride, s.rp, s.mask, s.alpha, nv);
         if ((rc = fused_r_update(F32, v.r, v.pin, v.q, s.alpha, o.nrows, nv, s.partial, s.rr_new, st))) return rc;
         if ((rc = d2h(h, s.rr_new, nv, st))) return rc;
         std::vector<double> rn(h, h + nv);
@@ -494,7 +509,7 @@ struct BiVecs {
     void* x;
     void *r, *rhat, *p, *v, *s, *t;
     dirac_prec p_;
-    const void* gauge;
+    Field f;
 };
 
 struct C {
@@ -524,7 +539,7 @@ int bicgstab_core(const OpCtx& o, const BiVecs& v, const Rules& ru, Scalars& s, 
     }
     auto residual = [&](std::vector<double>& rt) -> int {
         int e;
-        if ((e = apply_op(o, P, v.gauge, v.x, v.t, false, st))) return e;
+        if ((e = apply_op(o, P, v.f, v.x, v.t, false, st))) return e;
         if ((e = blas_sub(v.pb, v.b, P, v.t, P, v.r, n, st))) return e;
         if ((e = blas_norm2(P, v.r, o.nrows, nv, s.partial, s.tmpn, st))) return e;
         if ((e = d2h(h, s.tmpn, nv, st))) return e;
@@ -624,7 +639,7 @@ int bicgstab_core(const OpCtx& o, const BiVecs& v, const Rules& ru, Scalars& s, 
         if ((rc = upload(d_beta, beta))) return rc;
         if ((rc = upload(d_omega, om_act))) return rc;
         if ((rc = fused_bicg_p(P, v.p, v.r, v.v, d_beta, d_omega, o.nrows, nv, st))) return rc;
-        if ((rc = apply_op(o, P, v.gauge, v.p, v.v, false, st))) return rc;
+        if ((rc = apply_op(o, P, v.f, v.p, v.v, false, st))) return rc;
         if ((rc = dots(v.rhat, v.v, rv))) return rc;
         if ((rc = norms(v.v, vn))) return rc;
         for (int i = 0; i < nv; ++i) {
@@ -633,7 +648,7 @@ int bicgstab_core(const OpCtx& o, const BiVecs& v, const Rules& ru, Scalars& s, 
         }
         if ((rc = upload(d_alpha, alpha))) return rc;
         if ((rc = fused_bicg_s(P, v.s, v.r, v.v, d_alpha, o.nrows, nv, st))) return rc;
-        if ((rc = apply_op(o, P, v.gauge, v.s, v.t, false, st))) return rc;
+        if ((rc = apply_op(o, P, v.f, v.s, v.t, false, st))) return rc;
         if ((rc = dots(v.t, v.s, ts))) return rc;
         if ((rc = norms(v.t, tt))) return rc;
         for (int i = 0; i < nv; ++i) {
@@ -720,7 +735,7 @@ Layout layout_for(int solver, dirac_prec outer, dirac_prec inner, int scheme) {
 
 // Defect correction: repeat { r = b - A x in FP64; stop if converged; x += |r| * e with e the
 // inner-precision solution of A e = r/|r| } (the paper's "sp solver wrapped in a dp updater").
-int defect_correction(const OpCtx& o, int solver, dirac_prec inner, const void* gauge_hi, const void* gauge_lo,
+int defect_correction(const OpCtx& o, int solver, dirac_prec inner, const Field& f_hi, const Field& f_lo,
                       const void* b, void* x, double tol, int maxit, const Rules& ru, const dirac_solve_opts* opts,
                       Carver& c, Scalars& s, hipStream_t st, Result& res) {
     const int nv = o.nv;
@@ -758,9 +773,9 @@ int defect_correction(const OpCtx& o, int solver, dirac_prec inner, const void* 
     res.reason = 2;
     for (int outer_it = 0; outer_it <= max_outer; ++outer_it) {
         if (solver == 0) {
-            if ((rc = apply_normal(o, DIRAC_FP64, gauge_hi, x, r_hi, t_hi, st))) return rc;
+            if ((rc = apply_normal(o, DIRAC_FP64, f_hi, x, r_hi, t_hi, st))) return rc;
         } else {
-            if ((rc = apply_op(o, DIRAC_FP64, gauge_hi, x, r_hi, false, st))) return rc;
+            if ((rc = apply_op(o, DIRAC_FP64, f_hi, x, r_hi, false, st))) return rc;
         }
         if ((rc = blas_bminus(DIRAC_FP64, b, DIRAC_FP64, r_hi, o.nrows, nv, st))) return rc;
         if ((rc = blas_norm2(DIRAC_FP64, r_hi, o.nrows, nv, s.partial, s.tmpn, st))) return rc;
@@ -802,10 +817,10 @@ int defect_correction(const OpCtx& o, int solver, dirac_prec inner, const void* 
         Rules rr = ir;
         rr.maxit = std::max(1, maxit - total);
         if (solver == 0) {
-            CGVecs v{b_lo, DIRAC_FP32, x_lo, DIRAC_FP32, r_lo, DIRAC_FP32, p, q, t, inner, gauge_lo};
+            CGVecs v{b_lo, DIRAC_FP32, x_lo, DIRAC_FP32, r_lo, DIRAC_FP32, p, q, t, inner, f_lo};
             rc = cg_core(o, v, rr, s, st, inner_res, false);
         } else {
-            BiVecs v{b_lo, inner, x_lo, r_lo, rh, p, q, ss, t, inner, gauge_lo};
+            BiVecs v{b_lo, inner, x_lo, r_lo, rh, p, q, ss, t, inner, f_lo};
             rc = bicgstab_core(o, v, rr, s, st, inner_res);
         }
         if (rc) return rc;
@@ -827,7 +842,7 @@ int defect_correction(const OpCtx& o, int solver, dirac_prec inner, const void* 
 
 size_t solver_workspace_bytes(dirac_op op, int solver, dirac_prec outer, dirac_prec inner, int nc, int nv,
                               const Geom& g, int scheme) {
-    OpCtx o{op, nc, nv, g, 0.0, g.vol * nc * (op == DIRAC_STAGGERED ? 1 : 4)};
+    OpCtx o{op, nc, nv, g, 0.0, g.vol * nc * (op_four_spin(op) ? 4 : 1)};
     Layout l = layout_for(solver, outer, inner, scheme);
     Carver c{nullptr, 0};
     Scalars s;
@@ -840,13 +855,15 @@ size_t solver_workspace_bytes(dirac_op op, int solver, dirac_prec outer, dirac_p
 }
 
 int run_solver(int solver, dirac_op op, dirac_prec outer, dirac_prec inner, const void* gauge_hi,
-               const void* gauge_lo, const void* b, void* x, double mass, int nc, int nv, const Geom& g, double tol,
-               int maxit, void* workspace, size_t ws_bytes, dirac_solve_info* info, const dirac_solve_opts* opts,
-               hipStream_t st) {
+               const void* gauge_lo, const void* clov_hi, const void* clov_lo, const void* b, void* x, double mass,
+               int nc, int nv, const Geom& g, double tol, int maxit, void* workspace, size_t ws_bytes,
+               dirac_solve_info* info, const dirac_solve_opts* opts, hipStream_t st) {
     const int scheme = opts ? opts->mixed_scheme : 0;
     if (ws_bytes < solver_workspace_bytes(op, solver, outer, inner, nc, nv, g, scheme))
         return fail(DIRAC_EWORKSPACE, "solver workspace smaller than dirac_solver_workspace_bytes()");
-    OpCtx o{op, nc, nv, g, mass, g.vol * nc * (op == DIRAC_STAGGERED ? 1 : 4)};
+    OpCtx o{op, nc, nv, g, mass, g.vol * nc * (op_four_spin(op) ? 4 : 1)};
+    const Field f_hi{gauge_hi, clov_hi};
+    const Field f_lo{gauge_lo, clov_lo};
     // 256-byte align the carve base
     char* base = static_cast<char*>(workspace);
     const uintptr_t mis = reinterpret_cast<uintptr_t>(base) % kAlign;
@@ -866,13 +883,13 @@ int run_solver(int solver, dirac_op op, dirac_prec outer, dirac_prec inner, cons
     if (!mixed) {
         if (solver == 0) {
             CGVecs v{b, outer, x, outer, c.take(vec_bytes(o, outer)), outer, c.take(vec_bytes(o, outer)),
-                     c.take(vec_bytes(o, outer)), c.take(vec_bytes(o, outer)), outer, gauge_hi};
+                     c.take(vec_bytes(o, outer)), c.take(vec_bytes(o, outer)), outer, f_hi};
             v.pr = outer;
             rc = cg_core(o, v, ru, s, st, res, hist);
         } else {
             BiVecs v{b, outer, x, c.take(vec_bytes(o, outer)), c.take(vec_bytes(o, outer)), c.take(vec_bytes(o, outer)),
                      c.take(vec_bytes(o, outer)), c.take(vec_bytes(o, outer)), c.take(vec_bytes(o, outer)), outer,
-                     gauge_hi};
+                     f_hi};
             rc = bicgstab_core(o, v, ru, s, st, res);
         }
     } else if (solver == 0 && scheme == 0) {
@@ -888,11 +905,11 @@ int run_solver(int solver, dirac_op op, dirac_prec outer, dirac_prec inner, cons
         v.q = c.take(vec_bytes(o, inner));
         v.t = c.take(vec_bytes(o, inner));
         v.pin = inner;
-        v.g_hi = gauge_hi;
-        v.g_lo = gauge_lo;
+        v.f_hi = f_hi;
+        v.f_lo = f_lo;
         rc = cg_reliable(o, v, ru, delta, s, st, res);
     } else {
-        rc = defect_correction(o, solver, inner, gauge_hi, gauge_lo, b, x, tol, maxit, ru, opts, c, s, st, res);
+        rc = defect_correction(o, solver, inner, f_hi, f_lo, b, x, tol, maxit, ru, opts, c, s, st, res);
     }
     if (rc) return rc;
     DIRAC_HIP(hipStreamSynchronize(st));

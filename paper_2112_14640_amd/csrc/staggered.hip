@@ -5,6 +5,11 @@
 //
 // eta_mu(n) = (-1)^(x_0 + ... + x_{mu-1}) on 0-based coordinates.  One thread owns a site
 // and RB consecutive right-hand sides, so each link is loaded once per RB columns.
+//
+// The same kernels apply the Wilson Laplacian of Eq. app_wlap (flag lap):
+//   (-1/2 Delta^std + m^2/2) u(n) = (4 + m^2/2) u(n) - 1/2 sum_mu [U_mu(n) u(n+mu) + U_mu(n-mu)^+ u(n-mu)],
+// which acts on colour only: a Wilson-layout vector [colour][spin][rhs] is a colour vector with 4 N_v
+// columns.  With lap every hop has the coefficient -1/2 and no phase; the caller passes the diagonal.
 #include <type_traits>
 
 #include "common.h"
@@ -43,11 +48,11 @@ __device__ __forceinline__ void stag_hop(cx<typename P::R> (&acc)[RB][NC], const
     }
 }
 
-template <int NC, int RB, bool DAG, class P, bool LOOP>
+template <int NC, int RB, bool DAG, class P>
 __global__ __launch_bounds__(256) void staggered_kernel(const typename P::G* __restrict__ U,
                                                          const typename P::S* __restrict__ in,
                                                          typename P::S* __restrict__ out, typename P::R mass, Geom g,
-                                                         int nv, SiteOrder order) {
+                                                         int nv, SiteOrder order, int lap) {
     using R = typename P::R;
     const int nrg = nv / RB;
     const int64_t gid = logical_block() * blockDim.x + threadIdx.x;
@@ -65,18 +70,18 @@ __global__ __launch_bounds__(256) void staggered_kernel(const typename P::G* __r
 #pragma unroll
         for (int a = 0; a < NC; ++a) acc[k][a] = cscale(mass, io<R, typename P::S>::ld(centre + a * nv + k));
 
-    const R half = DAG ? R(-0.5) : R(0.5);
+    const R half = lap ? R(-0.5) : (DAG ? R(-0.5) : R(0.5));
+    const R bsign = lap ? R(1) : R(-1);  // backward hop coefficient relative to the forward one
     const int par[4] = {0, c.x & 1, (c.x + c.y) & 1, (c.x + c.y + c.z) & 1};
     const int64_t stride[4] = {1, g.nx, static_cast<int64_t>(g.nx) * g.ny, static_cast<int64_t>(g.nx) * g.ny * g.nz};
     const int coord[4] = {c.x, c.y, c.z, c.t};
     const int ext[4] = {g.nx, g.ny, g.nz, g.nt};
-    // LOOP: one direction per iteration (bounded live registers); else fully unrolled
-#pragma unroll(LOOP ? 1 : 4)
+#pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
-        const R eta = par[mu] ? -half : half;
+        const R eta = (par[mu] && !lap) ? -half : half;
         const int64_t fwd = site + (coord[mu] == ext[mu] - 1 ? (1 - ext[mu]) * stride[mu] : stride[mu]);
         const int64_t bwd = site - (coord[mu] == 0 ? (1 - ext[mu]) * stride[mu] : stride[mu]);
-        R sf = eta, sb = -eta;
+        R sf = eta, sb = bsign * eta;
         if (mu == 3 && g.apbc) {
             if (c.t == g.nt - 1) sf = -sf;
             if (c.t == 0) sb = -sb;
@@ -92,157 +97,6 @@ __global__ __launch_bounds__(256) void staggered_kernel(const typename P::G* __r
         for (int a = 0; a < NC; ++a) io<R, typename P::S>::st(o + a * nv + k, acc[k][a]);
 }
 
-// LDS-staged variant (see tile.h): neighbour blocks and links of a tile of S sites pass
-// through LDS so that every global load and store instruction is contiguous.
-template <int NC, int RB, bool DAG, class P, typename Unit>
-__global__ __launch_bounds__(512) void staggered_lds_kernel(const typename P::G* __restrict__ U,
-                                                             const typename P::S* __restrict__ in,
-                                                             typename P::S* __restrict__ out, typename P::R mass,
-                                                             Geom g, int nv, TileGeom tg) {
-    using R = typename P::R;
-    using S = typename P::S;
-    using G = typename P::G;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int St = tg.S;
-    constexpr int L = NC * NC;
-    int* nb = reinterpret_cast<int*>(smem);
-    size_t off = (static_cast<size_t>(kHopSlots) * St * sizeof(int) + 15) / 16 * 16;
-    G* lf = reinterpret_cast<G*>(smem + off);
-    off += (static_cast<size_t>(St) * 4 * L * sizeof(G) + 15) / 16 * 16;
-    G* lb = reinterpret_cast<G*>(smem + off);
-    off += (static_cast<size_t>(St) * L * sizeof(G) + 15) / 16 * 16;
-    Unit* tile = reinterpret_cast<Unit*>(smem + off);
-
-    const int64_t s0 = logical_block() * St;
-    if (s0 >= g.vol) return;
-    const int nsites = static_cast<int>(g.vol - s0 < St ? g.vol - s0 : St);
-    tile_neighbours(nb, s0, St, g);
-    {
-        const size_t bytes = static_cast<size_t>(nsites) * 4 * L * sizeof(G);
-        copy_in(reinterpret_cast<uint4*>(lf), reinterpret_cast<const uint4*>(U + s0 * 4 * L),
-                static_cast<uint32_t>(bytes / 16));
-    }
-    __syncthreads();  // the neighbour table is read by every thread below
-    const uint32_t tid = threadIdx.x;
-    const uint32_t j = fast_div(tid, tg.magic_nrg);
-    const int rg = static_cast<int>(tid - j * tg.nrg);
-    const bool active = j < static_cast<uint32_t>(nsites);
-    const int r0 = rg * RB;
-    int par[4] = {0, 0, 0, 0};
-    int ct = 0;
-    if (active) {
-        const Coord c = site_coord(s0 + j, g);
-        par[1] = c.x & 1;
-        par[2] = (c.x + c.y) & 1;
-        par[3] = (c.x + c.y + c.z) & 1;
-        ct = c.t;
-    }
-    const S* mine = reinterpret_cast<const S*>(tile + j * (tg.units + 1)) + r0;
-    const Unit* src = reinterpret_cast<const Unit*>(in);
-
-    cx<R> acc[RB][NC];
-    tile_gather(tile, src, nb, tg);
-    __syncthreads();
-    if (active) {
-#pragma unroll
-        for (int k = 0; k < RB; ++k)
-#pragma unroll
-            for (int a = 0; a < NC; ++a) acc[k][a] = cscale(mass, io<R, S>::ld(mine + a * nv + k));
-    }
-    const R half = DAG ? R(-0.5) : R(0.5);
-    auto direction = [&](auto mu_c) {
-        constexpr int MU = decltype(mu_c)::value;
-        const R eta = par[MU] ? -half : half;
-        R sf = eta, sb = -eta;
-        if (MU == 3 && g.apbc) {
-            if (ct == g.nt - 1) sf = -sf;
-            if (ct == 0) sb = -sb;
-        }
-        __syncthreads();
-        tile_gather(tile, src, nb + (1 + 2 * MU) * St, tg);
-        __syncthreads();
-        if (active) stag_hop<NC, RB, false, P>(acc, lf + (j * 4 + MU) * L, mine, nv, sf);
-        __syncthreads();
-        tile_gather(tile, src, nb + (2 + 2 * MU) * St, tg);
-        for (uint32_t u = tid; u < static_cast<uint32_t>(St * L); u += blockDim.x) {
-            const uint32_t jj = u / L;
-            const uint32_t e = u - jj * L;
-            lb[u] = U[(static_cast<int64_t>(nb[(2 + 2 * MU) * St + jj]) * 4 + MU) * L + e];
-        }
-        __syncthreads();
-        if (active) stag_hop<NC, RB, true, P>(acc, lb + j * L, mine, nv, sb);
-    };
-    direction(std::integral_constant<int, 0>{});
-    direction(std::integral_constant<int, 1>{});
-    direction(std::integral_constant<int, 2>{});
-    direction(std::integral_constant<int, 3>{});
-    __syncthreads();
-    if (active) {
-        S* o = const_cast<S*>(mine);
-#pragma unroll
-        for (int k = 0; k < RB; ++k)
-#pragma unroll
-            for (int a = 0; a < NC; ++a) io<R, S>::st(o + a * nv + k, acc[k][a]);
-    }
-    __syncthreads();
-    tile_scatter_out(reinterpret_cast<Unit*>(out) + s0 * tg.units, tile, nsites, tg);
-}
-
-template <int NC, int RB, class P, typename Unit>
-void launch_lds_unit(const StencilArgs& a, hipStream_t st, int units) {
-    using R = typename P::R;
-    using S = typename P::S;
-    using G = typename P::G;
-    const int nrg = a.nv / RB;
-    auto lds_of = [&](int s) { return lds_bytes(s, 4 * NC * NC * sizeof(G), NC * NC * sizeof(G), units, sizeof(Unit)); };
-    const int St = choose_tile_sites(nrg, lds_of);
-    TileGeom tg{St, nrg, units, div_magic(units), div_magic(nrg)};
-    const int threads = (St * nrg + 63) / 64 * 64;
-    const dim3 grid(static_cast<unsigned>(grid_blocks_x8(a.g.vol, St)));
-    auto U = static_cast<const G*>(a.gauge);
-    auto in = static_cast<const S*>(a.in);
-    auto out = static_cast<S*>(a.out);
-    const R m = static_cast<R>(a.mass);
-    if (a.dagger)
-        hipLaunchKernelGGL((staggered_lds_kernel<NC, RB, true, P, Unit>), grid, dim3(threads), lds_of(St), st, U, in,
-                           out, m, a.g, a.nv, tg);
-    else
-        hipLaunchKernelGGL((staggered_lds_kernel<NC, RB, false, P, Unit>), grid, dim3(threads), lds_of(St), st, U, in,
-                           out, m, a.g, a.nv, tg);
-}
-
-template <int NC, int RB, class P>
-bool launch_lds(const StencilArgs& a, hipStream_t st) {
-    using S = typename P::S;
-    using G = typename P::G;
-    const size_t block_bytes = static_cast<size_t>(NC) * a.nv * sizeof(S);
-    if (!tile_aligned(a)) return false;
-    const int nrg = a.nv / RB;
-    if (block_bytes % 16 == 0) {
-        const int units = static_cast<int>(block_bytes / 16);
-        if (!choose_tile_sites(nrg, [&](int s) {
-                return lds_bytes(s, 4 * NC * NC * sizeof(G), NC * NC * sizeof(G), units, 16);
-            }))
-            return false;
-        launch_lds_unit<NC, RB, P, uint4>(a, st, units);
-    } else if (block_bytes % 8 == 0) {
-        const int units = static_cast<int>(block_bytes / 8);
-        if (!choose_tile_sites(nrg, [&](int s) {
-                return lds_bytes(s, 4 * NC * NC * sizeof(G), NC * NC * sizeof(G), units, 8);
-            }))
-            return false;
-        launch_lds_unit<NC, RB, P, uint2>(a, st, units);
-    } else {
-        const int units = static_cast<int>(block_bytes / 4);
-        if (!choose_tile_sites(nrg, [&](int s) {
-                return lds_bytes(s, 4 * NC * NC * sizeof(G), NC * NC * sizeof(G), units, 4);
-            }))
-            return false;
-        launch_lds_unit<NC, RB, P, uint32_t>(a, st, units);
-    }
-    return true;
-}
-
 
 // Row-tiled variant: one x-row (every RHS) per work-group, the rows one step along +-y, +-z,
 // +-t staged in LDS one at a time with contiguous loads of Unit (16 or 8 bytes), the next row copy
@@ -251,7 +105,7 @@ template <int NC, int RB, bool DAG, class P, typename Unit, bool LL>
 __global__ __launch_bounds__(512) void staggered_rows_kernel(const typename P::G* __restrict__ U,
                                                              const typename P::S* __restrict__ in,
                                                              typename P::S* __restrict__ out, typename P::R mass,
-                                                             Geom g, int nv, RowTile rt) {
+                                                             Geom g, int nv, RowTile rt, int lap) {
     using R = typename P::R;
     using S = typename P::S;
     using G = typename P::G;
@@ -334,10 +188,11 @@ __global__ __launch_bounds__(512) void staggered_rows_kernel(const typename P::G
         }
     };
     cx<R> acc[RB][NC];
-    const R half = DAG ? R(-0.5) : R(0.5);
-    // eta_mu(n) = (-1)^(x_0 + ... + x_{mu-1})
-    const R eta[4] = {half, (x & 1) ? -half : half, ((x + cy) & 1) ? -half : half,
-                      ((x + cy + cz) & 1) ? -half : half};
+    const R half = lap ? R(-0.5) : (DAG ? R(-0.5) : R(0.5));
+    const R bsign = lap ? R(1) : R(-1);  // backward hop coefficient relative to the forward one
+    // eta_mu(n) = (-1)^(x_0 + ... + x_{mu-1}) (all 1 for the Laplacian)
+    const R eta[4] = {half, ((x & 1) && !lap) ? -half : half, (((x + cy) & 1) && !lap) ? -half : half,
+                      (((x + cy + cz) & 1) && !lap) ? -half : half};
     const int xp = x + 1 == g.nx ? 0 : x + 1;
     const int xm = x == 0 ? g.nx - 1 : x - 1;
     cx<R> lxp[NC][NC], lxm[NC][NC], lnext[NC][NC];
@@ -378,7 +233,7 @@ __global__ __launch_bounds__(512) void staggered_rows_kernel(const typename P::G
 #pragma unroll
             for (int a = 0; a < NC; ++a) acc[k][a] = cscale(mass, io<R, S>::ld(mine + a * nv + k));
         hop_acc(lxp, at(xp), eta[0]);
-        hop_acc(lxm, at(xm), -eta[0]);
+        hop_acc(lxm, at(xm), bsign * eta[0]);
     }
     auto step = [&](auto mu_c, auto back_c) __attribute__((always_inline)) {
         constexpr int MU = decltype(mu_c)::value;
@@ -409,7 +264,7 @@ __global__ __launch_bounds__(512) void staggered_rows_kernel(const typename P::G
         }
         if constexpr (LL) load_link(lcur, lwin + x * L, BACK);
         if (active) {
-            R sc = BACK ? -eta[MU] : eta[MU];
+            R sc = BACK ? bsign * eta[MU] : eta[MU];
             if (MU == 3 && g.apbc && ct == (BACK ? 0 : g.nt - 1)) sc = -sc;  // fermion sign
             hop_acc(lcur, at(j), sc);
         }
@@ -438,7 +293,7 @@ __global__ __launch_bounds__(512) void staggered_rows_kernel(const typename P::G
 }
 
 template <int NC, int RB, class P>
-bool launch_rows(const StencilArgs& a, hipStream_t st) {
+bool launch_rows(const StencilArgs& a, int nv, typename P::R diag, hipStream_t st) {
     using S = typename P::S;
     constexpr size_t share = static_cast<size_t>(NC) * RB * sizeof(S);  // bytes per thread per row copy
     constexpr size_t ub = share % 16 == 0 ? 16 : (share % 8 == 0 ? 8 : 0);
@@ -446,10 +301,10 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
         return false;
     } else {
         using Unit = std::conditional_t<ub == 16, u32x4, u32x2>;
-        const size_t block_bytes = static_cast<size_t>(NC) * a.nv * sizeof(S);
+        const size_t block_bytes = static_cast<size_t>(NC) * nv * sizeof(S);
         if (block_bytes % ub != 0 || !tile_aligned(a)) return false;
         const int units = static_cast<int>(block_bytes / ub);
-        const int nrg = a.nv / RB;
+        const int nrg = nv / RB;
         const int64_t rows = a.g.vol / a.g.nx;
         const int64_t threads = static_cast<int64_t>(a.g.nx) * nrg;
         const size_t lds = static_cast<size_t>(a.g.nx) * (units + 1) * ub;
@@ -462,6 +317,7 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
         rt.row_units = a.g.nx * units;
         rt.threads = static_cast<int>(threads);
         rt.ntiles = rows;
+        rt.nseg = 1;
         rt.magic_nrg = div_magic(nrg);
         rt.magic_nx = div_magic(a.g.nx);
         rt.magic_units = div_magic(units);
@@ -469,28 +325,28 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
         if (!row_order(4, a.g, rt)) return false;
         const int block = (rt.threads + 63) / 64 * 64;
         const dim3 grid(static_cast<unsigned>(grid_blocks_x8(rt.ntiles, 1)));
-        using R = typename P::R;
-        const R m = static_cast<R>(a.mass);
         auto U = static_cast<const typename P::G*>(a.gauge);
         auto in = static_cast<const S*>(a.in);
         auto out = static_cast<S*>(a.out);
-        // variant 8: each direction's links staged in LDS after the row tile (two entries per thread
-        // at most)
+        const int lap = a.laplace ? 1 : 0;
+        // FP32 and BF16: each direction's links staged in LDS after the row tile (at most two entries
+        // per thread); FP64 loads them per thread (its staged form touched scratch and ran slower)
         const size_t lds_ll = (lds + 15) / 16 * 16 + static_cast<size_t>(a.g.nx) * NC * NC * sizeof(typename P::G);
-        const bool ll = a.variant == 8 && static_cast<int64_t>(a.g.nx) * NC * NC <= 2 * threads && lds_ll <= 64 * 1024;
+        const bool ll = sizeof(typename P::R) == 4 && static_cast<int64_t>(a.g.nx) * NC * NC <= 2 * threads &&
+                        lds_ll <= 64 * 1024;
         if (ll) {
             if (a.dagger)
                 hipLaunchKernelGGL((staggered_rows_kernel<NC, RB, true, P, Unit, true>), grid, dim3(block), lds_ll, st,
-                                   U, in, out, m, a.g, a.nv, rt);
+                                   U, in, out, diag, a.g, nv, rt, lap);
             else
                 hipLaunchKernelGGL((staggered_rows_kernel<NC, RB, false, P, Unit, true>), grid, dim3(block), lds_ll, st,
-                                   U, in, out, m, a.g, a.nv, rt);
+                                   U, in, out, diag, a.g, nv, rt, lap);
         } else if (a.dagger) {
             hipLaunchKernelGGL((staggered_rows_kernel<NC, RB, true, P, Unit, false>), grid, dim3(block), lds, st, U, in,
-                               out, m, a.g, a.nv, rt);
+                               out, diag, a.g, nv, rt, lap);
         } else {
             hipLaunchKernelGGL((staggered_rows_kernel<NC, RB, false, P, Unit, false>), grid, dim3(block), lds, st, U,
-                               in, out, m, a.g, a.nv, rt);
+                               in, out, diag, a.g, nv, rt, lap);
         }
         return true;
     }
@@ -499,31 +355,24 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
 template <int NC, int RB, class P>
 void launch_rb(const StencilArgs& a, hipStream_t st) {
     using R = typename P::R;
-    if ((a.variant == 4 || a.variant == 8) && launch_rows<NC, RB, P>(a, st)) return;
-    if (use_lds_variant(a, false) && launch_lds<NC, RB, P>(a, st)) return;
+    // the Wilson Laplacian treats the spin index as four more columns per colour
+    const int nv = a.laplace ? 4 * a.nv : a.nv;
+    const R diag = static_cast<R>(a.laplace ? 4.0 + 0.5 * a.mass * a.mass : a.mass);
+    if (a.variant == 4 && launch_rows<NC, RB, P>(a, nv, diag, st)) return;
     const int block = 256;
-    const int64_t threads = a.g.vol * (a.nv / RB);
+    const int64_t threads = a.g.vol * (nv / RB);
     const dim3 grid(static_cast<unsigned>(grid_blocks_x8(threads, block)));
     auto U = static_cast<const typename P::G*>(a.gauge);
     auto in = static_cast<const typename P::S*>(a.in);
     auto out = static_cast<typename P::S*>(a.out);
-    const R m = static_cast<R>(a.mass);
     const SiteOrder ord = make_site_order(a.g);
-    if (a.variant == 3) {
-        if (a.dagger)
-            hipLaunchKernelGGL((staggered_kernel<NC, RB, true, P, true>), grid, dim3(block), 0, st, U, in, out, m, a.g,
-                               a.nv, ord);
-        else
-            hipLaunchKernelGGL((staggered_kernel<NC, RB, false, P, true>), grid, dim3(block), 0, st, U, in, out, m,
-                               a.g, a.nv, ord);
-    } else {
-        if (a.dagger)
-            hipLaunchKernelGGL((staggered_kernel<NC, RB, true, P, false>), grid, dim3(block), 0, st, U, in, out, m,
-                               a.g, a.nv, ord);
-        else
-            hipLaunchKernelGGL((staggered_kernel<NC, RB, false, P, false>), grid, dim3(block), 0, st, U, in, out, m,
-                               a.g, a.nv, ord);
-    }
+    const int lap = a.laplace ? 1 : 0;
+    if (a.dagger)
+        hipLaunchKernelGGL((staggered_kernel<NC, RB, true, P>), grid, dim3(block), 0, st, U, in, out, diag, a.g, nv,
+                           ord, lap);
+    else
+        hipLaunchKernelGGL((staggered_kernel<NC, RB, false, P>), grid, dim3(block), 0, st, U, in, out, diag, a.g, nv,
+                           ord, lap);
 }
 
 template <int NC, class P>

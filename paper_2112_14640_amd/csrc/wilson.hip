@@ -1,4 +1,5 @@
-// Wilson Dirac operator D_W and its adjoint (Sec. 5, Eq. app_wils; r = 1, c_SW = 0).
+// Wilson Dirac operator D_W and its adjoint (Sec. 5, Eq. app_wils; r = 1), with the optional clover
+// term C of Eq. def_clov added at the site (C is hermitian, so (D_W + C)^+ = D_W^+ + C):
 //
 //   (D_W u)(n)   = (4+m) u(n) - 1/2 sum_mu [(1 - g_mu) U_mu(n) u(n+mu) + (1 + g_mu) U_mu(n-mu)^+ u(n-mu)]
 //   (D_W^+ u)(n) = (4+m) u(n) - 1/2 sum_mu [(1 + g_mu) U_mu(n) u(n+mu) + (1 - g_mu) U_mu(n-mu)^+ u(n-mu)]
@@ -11,6 +12,7 @@
 // antiperiodic in t.
 #include <type_traits>
 
+#include "clover.h"
 #include "common.h"
 #include "kernels.h"
 #include "tile.h"
@@ -134,15 +136,6 @@ __device__ __forceinline__ void hop_with(cx<typename P::R> (&acc)[RB][NC][4], co
     }
 }
 
-// acc += scale * (1 + SIG g_MU) L u_nb, with L = link (ADJ = false) or link^+ (ADJ = true).
-template <int NC, int RB, int MU, int SIG, bool ADJ, class P>
-__device__ __forceinline__ void hop(cx<typename P::R> (&acc)[RB][NC][4], const typename P::G* __restrict__ link,
-                                    const typename P::S* __restrict__ nb, int nv, typename P::R scale) {
-    cx<typename P::R> l[NC][NC];
-    load_link<NC, ADJ, P>(l, link);
-    hop_with<NC, RB, MU, SIG, P>(acc, l, nb, nv, scale);
-}
-
 // Direction-generic hop (runtime mu and projector sign, wave-uniform).  With P = 1 + sig g_mu
 // in the chiral basis the half spinor is h0 = p0 + c0 p_A, h1 = p1 + c1 p_B and the full spinor
 // is rebuilt as (h0, h1, e2 h_C, e3 h_D), where every c, e is one of +-1, +-i:
@@ -213,44 +206,14 @@ __device__ __forceinline__ void hop_rt(cx<typename P::R> (&acc)[RB][NC][4], cons
     }
 }
 
-template <int NC, int RB, int MU, bool DAG, class P>
-__device__ __forceinline__ void both_hops(cx<typename P::R> (&acc)[RB][NC][4], const typename P::G* __restrict__ U,
-                                          const typename P::S* __restrict__ in, int64_t site, const Coord& c,
-                                          const Geom& g, int nv, int r0) {
-    using R = typename P::R;
-    int64_t fwd, bwd;
-    R sf = R(-0.5), sb = R(-0.5);
-    if constexpr (MU == 0) {
-        fwd = site + (c.x == g.nx - 1 ? 1 - g.nx : 1);
-        bwd = site - (c.x == 0 ? 1 - g.nx : 1);
-    } else if constexpr (MU == 1) {
-        const int64_t st = g.nx;
-        fwd = site + (c.y == g.ny - 1 ? (1 - g.ny) * st : st);
-        bwd = site - (c.y == 0 ? (1 - g.ny) * st : st);
-    } else if constexpr (MU == 2) {
-        const int64_t st = static_cast<int64_t>(g.nx) * g.ny;
-        fwd = site + (c.z == g.nz - 1 ? (1 - g.nz) * st : st);
-        bwd = site - (c.z == 0 ? (1 - g.nz) * st : st);
-    } else {
-        const int64_t st = static_cast<int64_t>(g.nx) * g.ny * g.nz;
-        fwd = site + (c.t == g.nt - 1 ? (1 - g.nt) * st : st);
-        bwd = site - (c.t == 0 ? (1 - g.nt) * st : st);
-        if (g.apbc) {
-            if (c.t == g.nt - 1) sf = R(0.5);
-            if (c.t == 0) sb = R(0.5);
-        }
-    }
-    const int64_t vs = static_cast<int64_t>(NC) * 4 * nv;
-    constexpr int SF = DAG ? 1 : -1;  // forward projector 1 + SF g_mu
-    hop<NC, RB, MU, SF, false, P>(acc, U + (site * 4 + MU) * NC * NC, in + fwd * vs + r0, nv, sf);
-    hop<NC, RB, MU, -SF, true, P>(acc, U + (bwd * 4 + MU) * NC * NC, in + bwd * vs + r0, nv, sb);
-}
-
-template <int NC, int RB, bool DAG, class P, bool LOOP>
+// Direct form: one thread per (site, RB right-hand sides), neighbours read from global memory, one
+// hop direction per loop iteration (only its loads are live, which keeps the register count and so
+// the waves per SIMD moderate).  It serves the shapes the row tiles cannot take.
+template <int NC, int RB, bool DAG, class P>
 __global__ __launch_bounds__(256) void wilson_kernel(const typename P::G* __restrict__ U,
                                                       const typename P::S* __restrict__ in,
                                                       typename P::S* __restrict__ out, typename P::R diag, Geom g,
-                                                      int nv, SiteOrder order) {
+                                                      int nv, SiteOrder order, const typename P::R* __restrict__ clov) {
     using R = typename P::R;
     const int nrg = nv / RB;
     const int64_t gid = logical_block() * blockDim.x + threadIdx.x;
@@ -270,39 +233,31 @@ __global__ __launch_bounds__(256) void wilson_kernel(const typename P::G* __rest
 #pragma unroll
             for (int s = 0; s < 4; ++s)
                 acc[k][a][s] = cscale(diag, io<R, typename P::S>::ld(centre + (a * 4 + s) * nv + k));
+    if (clov) clover_add<NC, RB>(acc, centre, nv, clov + site * clover_reals<NC>());
 
-    if constexpr (LOOP) {
-        // one hop per iteration: only its loads are live, which keeps the register count (and
-        // so the number of waves per SIMD hiding memory latency) moderate
-        const int co[4] = {c.x, c.y, c.z, c.t};
-        const int ext[4] = {g.nx, g.ny, g.nz, g.nt};
+    const int co[4] = {c.x, c.y, c.z, c.t};
+    const int ext[4] = {g.nx, g.ny, g.nz, g.nt};
 #pragma nounroll
-        for (int d = 0; d < 8; ++d) {
-            const int mu = d >> 1;
-            const bool back = d & 1;
-            const int64_t stride = mu == 0 ? 1 : (mu == 1 ? g.nx : (mu == 2 ? static_cast<int64_t>(g.nx) * g.ny
-                                                                             : static_cast<int64_t>(g.nx) * g.ny * g.nz));
-            const int cm = mu == 0 ? co[0] : (mu == 1 ? co[1] : (mu == 2 ? co[2] : co[3]));
-            const int em = mu == 0 ? ext[0] : (mu == 1 ? ext[1] : (mu == 2 ? ext[2] : ext[3]));
-            int64_t nbs;
-            typename P::R scale = typename P::R(-0.5);
-            if (!back) {
-                nbs = site + (cm == em - 1 ? (1 - em) * stride : stride);
-                if (mu == 3 && g.apbc && cm == em - 1) scale = typename P::R(0.5);
-            } else {
-                nbs = site - (cm == 0 ? (1 - em) * stride : stride);
-                if (mu == 3 && g.apbc && cm == 0) scale = typename P::R(0.5);
-            }
-            // D: forward (1 - g_mu), backward (1 + g_mu); the adjoint swaps them
-            const int sig = (back != DAG) ? 1 : -1;
-            const typename P::G* link = U + ((back ? nbs : site) * 4 + mu) * NC * NC;
-            hop_rt<NC, RB, P>(acc, link, back, in + nbs * vs + r0, nv, scale, mu, sig);
+    for (int d = 0; d < 8; ++d) {
+        const int mu = d >> 1;
+        const bool back = d & 1;
+        const int64_t stride = mu == 0 ? 1 : (mu == 1 ? g.nx : (mu == 2 ? static_cast<int64_t>(g.nx) * g.ny
+                                                                         : static_cast<int64_t>(g.nx) * g.ny * g.nz));
+        const int cm = mu == 0 ? co[0] : (mu == 1 ? co[1] : (mu == 2 ? co[2] : co[3]));
+        const int em = mu == 0 ? ext[0] : (mu == 1 ? ext[1] : (mu == 2 ? ext[2] : ext[3]));
+        int64_t nbs;
+        R scale = R(-0.5);
+        if (!back) {
+            nbs = site + (cm == em - 1 ? (1 - em) * stride : stride);
+            if (mu == 3 && g.apbc && cm == em - 1) scale = R(0.5);
+        } else {
+            nbs = site - (cm == 0 ? (1 - em) * stride : stride);
+            if (mu == 3 && g.apbc && cm == 0) scale = R(0.5);
         }
-    } else {
-        both_hops<NC, RB, 0, DAG, P>(acc, U, in, site, c, g, nv, r0);
-        both_hops<NC, RB, 1, DAG, P>(acc, U, in, site, c, g, nv, r0);
-        both_hops<NC, RB, 2, DAG, P>(acc, U, in, site, c, g, nv, r0);
-        both_hops<NC, RB, 3, DAG, P>(acc, U, in, site, c, g, nv, r0);
+        // D: forward (1 - g_mu), backward (1 + g_mu); the adjoint swaps them
+        const int sig = (back != DAG) ? 1 : -1;
+        const typename P::G* link = U + ((back ? nbs : site) * 4 + mu) * NC * NC;
+        hop_rt<NC, RB, P>(acc, link, back, in + nbs * vs + r0, nv, scale, mu, sig);
     }
 
     typename P::S* o = out + site * vs + r0;
@@ -314,112 +269,18 @@ __global__ __launch_bounds__(256) void wilson_kernel(const typename P::G* __rest
             for (int s = 0; s < 4; ++s) io<R, typename P::S>::st(o + (a * 4 + s) * nv + k, acc[k][a][s]);
 }
 
-// LDS-staged variant: the work-group owns S consecutive sites; per hop direction the S
-// neighbour blocks are gathered into LDS with contiguous loads, the tile's forward links
-// live in LDS for the whole kernel and the backward links of the current direction are
-// gathered next to the spinors; the output tile leaves through LDS as contiguous stores.
-template <int NC, int RB, bool DAG, class P, typename Unit>
-__global__ __launch_bounds__(512) void wilson_lds_kernel(const typename P::G* __restrict__ U,
-                                                          const typename P::S* __restrict__ in,
-                                                          typename P::S* __restrict__ out, typename P::R diag, Geom g,
-                                                          int nv, TileGeom tg) {
-    using R = typename P::R;
-    using S = typename P::S;
-    using G = typename P::G;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int St = tg.S;
-    constexpr int L = NC * NC;
-    int* nb = reinterpret_cast<int*>(smem);
-    size_t off = (static_cast<size_t>(kHopSlots) * St * sizeof(int) + 15) / 16 * 16;
-    G* lf = reinterpret_cast<G*>(smem + off);
-    off += (static_cast<size_t>(St) * 4 * L * sizeof(G) + 15) / 16 * 16;
-    G* lb = reinterpret_cast<G*>(smem + off);
-    off += (static_cast<size_t>(St) * L * sizeof(G) + 15) / 16 * 16;
-    Unit* tile = reinterpret_cast<Unit*>(smem + off);
-
-    const int64_t s0 = logical_block() * St;
-    if (s0 >= g.vol) return;
-    const int nsites = static_cast<int>(g.vol - s0 < St ? g.vol - s0 : St);
-    tile_neighbours(nb, s0, St, g);
-    {
-        const size_t bytes = static_cast<size_t>(nsites) * 4 * L * sizeof(G);
-        copy_in(reinterpret_cast<uint4*>(lf), reinterpret_cast<const uint4*>(U + s0 * 4 * L),
-                static_cast<uint32_t>(bytes / 16));
-    }
-    __syncthreads();  // the neighbour table is read by every thread below
-    const uint32_t tid = threadIdx.x;
-    const uint32_t j = fast_div(tid, tg.magic_nrg);
-    const int rg = static_cast<int>(tid - j * tg.nrg);
-    const bool active = j < static_cast<uint32_t>(nsites);
-    const int r0 = rg * RB;
-    int ct = 0;
-    if (active) ct = site_coord(s0 + j, g).t;
-    const S* mine = reinterpret_cast<const S*>(tile + j * (tg.units + 1)) + r0;
-    const Unit* src = reinterpret_cast<const Unit*>(in);
-
-    cx<R> acc[RB][NC][4];
-    tile_gather(tile, src, nb, tg);
-    __syncthreads();
-    if (active) {
-#pragma unroll
-        for (int k = 0; k < RB; ++k)
-#pragma unroll
-            for (int a = 0; a < NC; ++a)
-#pragma unroll
-                for (int s = 0; s < 4; ++s) acc[k][a][s] = cscale(diag, io<R, S>::ld(mine + (a * 4 + s) * nv + k));
-    }
-    constexpr int SF = DAG ? 1 : -1;  // forward projector 1 + SF g_mu
-    auto direction = [&](auto mu_c) {
-        constexpr int MU = decltype(mu_c)::value;
-        R sf = R(-0.5), sb = R(-0.5);
-        if (MU == 3 && g.apbc) {
-            if (ct == g.nt - 1) sf = R(0.5);
-            if (ct == 0) sb = R(0.5);
-        }
-        __syncthreads();
-        tile_gather(tile, src, nb + (1 + 2 * MU) * St, tg);
-        __syncthreads();
-        if (active) hop<NC, RB, MU, SF, false, P>(acc, lf + (j * 4 + MU) * L, mine, nv, sf);
-        __syncthreads();
-        tile_gather(tile, src, nb + (2 + 2 * MU) * St, tg);
-        for (uint32_t u = tid; u < static_cast<uint32_t>(St * L); u += blockDim.x) {
-            const uint32_t jj = u / L;
-            const uint32_t e = u - jj * L;
-            lb[u] = U[(static_cast<int64_t>(nb[(2 + 2 * MU) * St + jj]) * 4 + MU) * L + e];
-        }
-        __syncthreads();
-        if (active) hop<NC, RB, MU, -SF, true, P>(acc, lb + j * L, mine, nv, sb);
-    };
-    direction(std::integral_constant<int, 0>{});
-    direction(std::integral_constant<int, 1>{});
-    direction(std::integral_constant<int, 2>{});
-    direction(std::integral_constant<int, 3>{});
-    __syncthreads();
-    if (active) {
-        S* o = const_cast<S*>(mine);
-#pragma unroll
-        for (int k = 0; k < RB; ++k)
-#pragma unroll
-            for (int a = 0; a < NC; ++a)
-#pragma unroll
-                for (int s = 0; s < 4; ++s) io<R, S>::st(o + (a * 4 + s) * nv + k, acc[k][a][s]);
-    }
-    __syncthreads();
-    tile_scatter_out(reinterpret_cast<Unit*>(out) + s0 * tg.units, tile, nsites, tg);
-}
-
-
 // Row-tiled variant (see RowTile).  Seven row copies per tile: the own rows (mass term and the
 // +-x hops) and the rows one step away in +y, -y, +z, -z, +t, -t.  The copy of the next
 // direction is issued into registers before the current direction is consumed from LDS, so the
 // loads of one direction overlap the arithmetic of the previous one.  The output tile leaves
 // through LDS as one contiguous store.
 
-template <int NC, int RB, bool DAG, class P, int NVC, bool LL>
+template <int NC, int RB, bool DAG, class P, int NVC, bool LL, bool CLOV>
 __global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* __restrict__ U,
                                                           const typename P::S* __restrict__ in,
                                                           typename P::S* __restrict__ out, typename P::R diag,
-                                                          Geom g, int nv, RowTile rt) {
+                                                          Geom g, int nv, RowTile rt,
+                                                          const typename P::R* __restrict__ clov) {
     using R = typename P::R;
     using S = typename P::S;
     constexpr int PER = RowUnits<NC, RB, P>::PER;
@@ -513,6 +374,20 @@ __global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* _
     if constexpr (LL) lstash();
     __syncthreads();
     fetch(row_neighbour_start(pos, 0, g));
+    auto mass_term = [&]() __attribute__((always_inline)) {
+        const S* mine = at(j);
+#pragma unroll
+        for (int k = 0; k < RB; ++k)
+#pragma unroll
+            for (int a = 0; a < NC; ++a)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) acc[k][a][s] = cscale(diag, io<R, S>::ld(mine + (a * 4 + s) * nv + k));
+        if constexpr (CLOV) clover_add<NC, RB>(acc, mine, nv, clov + site * clover_reals<NC>());
+    };
+    // with a clover field the site's clover block is applied from the own row before the x links are
+    // taken into registers
+    if constexpr (CLOV)
+        if (active) mass_term();
     if constexpr (LL) {
         lfetch(rowsite, 1);
         load_link<NC, false, P>(lxp, lwin + x * L);
@@ -523,13 +398,7 @@ __global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* _
     // each transported half spinor enters the sum with -1/2 (+1/2 across the antiperiodic t
     // boundary) as the multiplier of the rebuild's multiply-adds
     if (active) {
-        const S* mine = at(j);
-#pragma unroll
-        for (int k = 0; k < RB; ++k)
-#pragma unroll
-            for (int a = 0; a < NC; ++a)
-#pragma unroll
-                for (int s = 0; s < 4; ++s) acc[k][a][s] = cscale(diag, io<R, S>::ld(mine + (a * 4 + s) * nv + k));
+        if constexpr (!CLOV) mass_term();
         hop_with<NC, RB, 0, SF, P, NVC>(acc, lxp, at(xp), nv, R(-0.5));
         hop_with<NC, RB, 0, -SF, P, NVC>(acc, lxm, at(xm), nv, R(-0.5));
     }
@@ -612,22 +481,25 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
     rt.row_units = a.g.nx * units;
     rt.threads = rt.S * nrg;
     rt.ntiles = rows / Rr;
+    rt.nseg = 1;
     rt.magic_nrg = div_magic(nrg);
     rt.magic_nx = div_magic(a.g.nx);
     rt.magic_units = div_magic(units);
     rt.magic_row_units = div_magic(rt.row_units);
-    if (!row_order(a.variant, a.g, rt)) return false;
+    if (!row_order(4, a.g, rt)) return false;
     const int block = (rt.threads + 63) / 64 * 64;
     size_t lds = row_tile_lds(rt.S, units);
-    // variant 8 also stages each direction's links: N_c^2 entries per site after the row tile
+    // with N_v = 12 and one RHS per thread each direction's links are staged in LDS too: N_c^2
+    // entries per site after the row tile
     const size_t lds_ll = lds + (static_cast<size_t>(rt.S) * NC * NC * sizeof(typename P::G) + 15) / 16 * 16;
-    const bool ll = a.variant == 8 && a.nv == 12 && RB == 1 && lds_ll <= kRowLdsCap && lds_ll <= max_lds_per_block();
+    const bool ll = a.nv == 12 && RB == 1 && lds_ll <= kRowLdsCap && lds_ll <= max_lds_per_block();
     const dim3 grid(static_cast<unsigned>(grid_blocks_x8(rt.ntiles, 1)));
     using R = typename P::R;
     const R diag = static_cast<R>(4.0 + a.mass);
     auto U = static_cast<const typename P::G*>(a.gauge);
     auto in = static_cast<const S*>(a.in);
     auto out = static_cast<S*>(a.out);
+    auto clov = static_cast<const R*>(a.clover);
     bool ok = true;
     auto go = [&](auto kern) {
         static const bool allowed = allow_lds(kern, kRowLdsCap);
@@ -635,69 +507,40 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
             ok = false;
             return;
         }
-        hipLaunchKernelGGL(kern, grid, dim3(block), lds, st, U, in, out, diag, a.g, a.nv, rt);
+        hipLaunchKernelGGL(kern, grid, dim3(block), lds, st, U, in, out, diag, a.g, a.nv, rt, clov);
     };
-    if (ll) {  // links staged in LDS with the rows (nv = 12)
-        lds = lds_ll;
+    // the clover term is a separate instantiation: its registers would otherwise lower the occupancy
+    // of the plain kernel
+    auto pick = [&](auto clov_c) {
+        constexpr bool CL = decltype(clov_c)::value;
+        if constexpr (RB == 1) {
+            if (ll) {  // links staged in LDS with the rows, RHS stride fixed at 12
+                lds = lds_ll;
+                if (a.dagger)
+                    go(wilson_rows_kernel<NC, RB, true, P, 12, true, CL>);
+                else
+                    go(wilson_rows_kernel<NC, RB, false, P, 12, true, CL>);
+                return;
+            }
+        }
+        // runtime RHS stride, links loaded by every thread
         if (a.dagger)
-            go(wilson_rows_kernel<NC, RB, true, P, 12, true>);
+            go(wilson_rows_kernel<NC, RB, true, P, 0, false, CL>);
         else
-            go(wilson_rows_kernel<NC, RB, false, P, 12, true>);
-    } else if (a.variant == 4 && a.nv == 12 && RB == 1) {  // the common multi-RHS count: constant offsets
-        if (a.dagger)
-            go(wilson_rows_kernel<NC, RB, true, P, 12, false>);
-        else
-            go(wilson_rows_kernel<NC, RB, false, P, 12, false>);
-    } else {  // runtime RHS stride
-        if (a.dagger)
-            go(wilson_rows_kernel<NC, RB, true, P, 0, false>);
-        else
-            go(wilson_rows_kernel<NC, RB, false, P, 0, false>);
-    }
-    return ok;
-}
-
-template <int NC, int RB, class P>
-bool launch_lds(const StencilArgs& a, hipStream_t st) {
-    using R = typename P::R;
-    using S = typename P::S;
-    using G = typename P::G;
-    const int nrg = a.nv / RB;
-    const size_t block_bytes = static_cast<size_t>(NC) * 4 * a.nv * sizeof(S);
-    if (block_bytes % 16 != 0 || !tile_aligned(a)) return false;
-    const int units = static_cast<int>(block_bytes / 16);
-    const int St = choose_tile_sites(nrg, [&](int s) {
-        return lds_bytes(s, 4 * NC * NC * sizeof(G), NC * NC * sizeof(G), units, 16);
-    });
-    if (St == 0) return false;
-    TileGeom tg{St, nrg, units, div_magic(units), div_magic(nrg)};
-    const int threads = (St * nrg + 63) / 64 * 64;
-    const size_t lds = lds_bytes(St, 4 * NC * NC * sizeof(G), NC * NC * sizeof(G), units, 16);
-    const dim3 grid(static_cast<unsigned>(grid_blocks_x8(a.g.vol, St)));
-    const R diag = static_cast<R>(4.0 + a.mass);
-    auto U = static_cast<const G*>(a.gauge);
-    auto in = static_cast<const S*>(a.in);
-    auto out = static_cast<S*>(a.out);
-    if (a.dagger)
-        hipLaunchKernelGGL((wilson_lds_kernel<NC, RB, true, P, uint4>), grid, dim3(threads), lds, st, U, in, out, diag,
-                           a.g, a.nv, tg);
+            go(wilson_rows_kernel<NC, RB, false, P, 0, false, CL>);
+    };
+    if (clov)
+        pick(std::true_type{});
     else
-        hipLaunchKernelGGL((wilson_lds_kernel<NC, RB, false, P, uint4>), grid, dim3(threads), lds, st, U, in, out,
-                           diag, a.g, a.nv, tg);
-    return true;
+        pick(std::false_type{});
+    return ok;
 }
 
 template <int NC, int RB, class P>
 void launch_rb(const StencilArgs& a, hipStream_t st) {
     using R = typename P::R;
-    if (a.variant >= 4 && a.variant <= 8) {
-        if (launch_rows<NC, RB, P>(a, st)) return;
-        StencilArgs b = a;  // the row tile does not fit: direct loads, one hop per iteration
-        b.variant = 3;
-        launch_rb<NC, RB, P>(b, st);
-        return;
-    }
-    if (use_lds_variant(a) && launch_lds<NC, RB, P>(a, st)) return;
+    if (a.variant == 4 && launch_rows<NC, RB, P>(a, st)) return;
+    // direct loads (selected, or the row tile does not fit this shape)
     const int block = 256;
     const int64_t threads = a.g.vol * (a.nv / RB);
     const dim3 grid(static_cast<unsigned>(grid_blocks_x8(threads, block)));
@@ -705,31 +548,22 @@ void launch_rb(const StencilArgs& a, hipStream_t st) {
     auto U = static_cast<const typename P::G*>(a.gauge);
     auto in = static_cast<const typename P::S*>(a.in);
     auto out = static_cast<typename P::S*>(a.out);
+    auto clov = static_cast<const R*>(a.clover);
     const SiteOrder ord = make_site_order(a.g);
-    if (a.variant == 3) {
-        if (a.dagger)
-            hipLaunchKernelGGL((wilson_kernel<NC, RB, true, P, true>), grid, dim3(block), 0, st, U, in, out, diag, a.g,
-                               a.nv, ord);
-        else
-            hipLaunchKernelGGL((wilson_kernel<NC, RB, false, P, true>), grid, dim3(block), 0, st, U, in, out, diag,
-                               a.g, a.nv, ord);
-    } else {
-        if (a.dagger)
-            hipLaunchKernelGGL((wilson_kernel<NC, RB, true, P, false>), grid, dim3(block), 0, st, U, in, out, diag,
-                               a.g, a.nv, ord);
-        else
-            hipLaunchKernelGGL((wilson_kernel<NC, RB, false, P, false>), grid, dim3(block), 0, st, U, in, out, diag,
-                               a.g, a.nv, ord);
-    }
+    if (a.dagger)
+        hipLaunchKernelGGL((wilson_kernel<NC, RB, true, P>), grid, dim3(block), 0, st, U, in, out, diag, a.g, a.nv, ord,
+                           clov);
+    else
+        hipLaunchKernelGGL((wilson_kernel<NC, RB, false, P>), grid, dim3(block), 0, st, U, in, out, diag, a.g, a.nv,
+                           ord, clov);
 }
 
 template <int NC, class P>
 void launch_nc(const StencilArgs& a, hipStream_t st) {
-    switch (a.rb) {
-        case 4: launch_rb<NC, 4, P>(a, st); break;
-        case 2: launch_rb<NC, 2, P>(a, st); break;
-        default: launch_rb<NC, 1, P>(a, st); break;
-    }
+    if (a.rb == 2)
+        launch_rb<NC, 2, P>(a, st);
+    else
+        launch_rb<NC, 1, P>(a, st);
 }
 
 template <class P>

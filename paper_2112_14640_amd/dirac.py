@@ -8,8 +8,12 @@ Layouts (x fastest among sites, right-hand-side index fastest inside a site):
 
 * gauge ``U``: (Nt, Nz, Ny, Nx, 4, Nc, Nc) complex
 * Brillouin links ``W``: (Nt, Nz, Ny, Nx, 40, Nc, Nc) complex (from ``brillouin_links``)
-* Wilson/Brillouin vectors: (Nt, Nz, Ny, Nx, Nc, 4, Nv)
+* clover field: (Nt, Nz, Ny, Nx, 8 Nc^2) real (from ``clover_field``), float64 or float32
+* Wilson/Brillouin vectors (also for the two Laplacians): (Nt, Nz, Ny, Nx, Nc, 4, Nv)
 * staggered vectors: (Nt, Nz, Ny, Nx, Nc, Nv)
+
+Operators: "wilson", "brillouin", "staggered", and the hermitian Laplacians "wilson_laplace"
+(gauge U) and "brillouin_laplace" (gauge W).
 
 Precision follows the vector dtype: complex128 -> FP64 (complex128 gauge),
 complex64 -> FP32 (complex64 gauge), bfloat16 with a trailing (re, im) axis of
@@ -24,7 +28,8 @@ import torch
 
 from . import _lib as L
 
-OPS = {"wilson": L.WILSON, "brillouin": L.BRILLOUIN, "staggered": L.STAGGERED}
+OPS = {"wilson": L.WILSON, "brillouin": L.BRILLOUIN, "staggered": L.STAGGERED, "wilson_laplace": L.WILSON_LAPLACE,
+       "brillouin_laplace": L.BRILLOUIN_LAPLACE}
 PREC_NAMES = {L.FP64: "fp64", L.FP32: "fp32", L.BF16: "bf16"}
 _PRECS = {v: k for k, v in PREC_NAMES.items()}
 
@@ -124,7 +129,7 @@ def geometry(op, u: torch.Tensor, antiperiodic_t=True) -> Geometry:
 def _check_gauge(g: Geometry, gauge: torch.Tensor, name="gauge", device=None):
     _require(gauge, name, device)
     nx, ny, nz, nt = g.dims
-    dirs = 40 if g.op == L.BRILLOUIN else 4
+    dirs = 40 if g.op in (L.BRILLOUIN, L.BRILLOUIN_LAPLACE) else 4
     want = (nt, nz, ny, nx, dirs, g.nc, g.nc)
     if tuple(gauge.shape) != want:
         raise ValueError(f"{name} shape {tuple(gauge.shape)} != {want}")
@@ -132,7 +137,23 @@ def _check_gauge(g: Geometry, gauge: torch.Tensor, name="gauge", device=None):
         raise TypeError(f"{name} dtype {gauge.dtype} != {_gauge_dtype(g.prec)} for {PREC_NAMES[g.prec]} vectors")
 
 
-def _apply(fn, op, gauge, u, mass, antiperiodic_t, out):
+def _clover_dtype(prec: int):
+    return torch.float64 if prec == L.FP64 else torch.float32
+
+
+def _check_clover(g: Geometry, clover: torch.Tensor, name="clover", device=None):
+    _require(clover, name, device)
+    if g.op not in (L.WILSON, L.BRILLOUIN):
+        raise ValueError("the clover term belongs to the Wilson and Brillouin operators")
+    nx, ny, nz, nt = g.dims
+    want = (nt, nz, ny, nx, 8 * g.nc * g.nc)
+    if tuple(clover.shape) != want:
+        raise ValueError(f"{name} shape {tuple(clover.shape)} != {want}")
+    if clover.dtype != _clover_dtype(g.prec):
+        raise TypeError(f"{name} dtype {clover.dtype} != {_clover_dtype(g.prec)} for {PREC_NAMES[g.prec]} vectors")
+
+
+def _apply(fn, op, gauge, u, mass, antiperiodic_t, out, clover=None):
     _require(u, "u")
     g = geometry(op, u, antiperiodic_t)
     _check_gauge(g, gauge, device=u.device)
@@ -142,19 +163,52 @@ def _apply(fn, op, gauge, u, mass, antiperiodic_t, out):
         _require_like(out, "out", u)
     lib = L.load()
     d = g.cdims()
-    L.check(getattr(lib, fn)(g.op, g.prec, _ptr(gauge), _ptr(u), _ptr(out), float(mass), g.nc, g.nv, C.byref(d),
-                             _stream()), fn)
+    if clover is None:
+        L.check(getattr(lib, fn)(g.op, g.prec, _ptr(gauge), _ptr(u), _ptr(out), float(mass), g.nc, g.nv, C.byref(d),
+                                 _stream()), fn)
+    else:
+        _check_clover(g, clover, device=u.device)
+        fn = fn.replace("dirac_apply", "dirac_apply_clover")
+        L.check(getattr(lib, fn)(g.op, g.prec, _ptr(gauge), _ptr(clover), _ptr(u), _ptr(out), float(mass), g.nc,
+                                 g.nv, C.byref(d), _stream()), fn)
     return out
 
 
-def apply(op, gauge, u, mass, antiperiodic_t=True, out=None):
-    """v = D u for op in {"wilson", "brillouin", "staggered"} (gauge = U, or W for Brillouin)."""
-    return _apply("dirac_apply", op, gauge, u, mass, antiperiodic_t, out)
+def apply(op, gauge, u, mass, antiperiodic_t=True, out=None, clover=None):
+    """v = D u for op in OPS (gauge = U, or W for the Brillouin operators); with ``clover`` (Wilson,
+    Brillouin) v = (D + C) u."""
+    return _apply("dirac_apply", op, gauge, u, mass, antiperiodic_t, out, clover)
 
 
-def apply_dagger(op, gauge, u, mass, antiperiodic_t=True, out=None):
-    """v = D^dagger u."""
-    return _apply("dirac_apply_dagger", op, gauge, u, mass, antiperiodic_t, out)
+def apply_dagger(op, gauge, u, mass, antiperiodic_t=True, out=None, clover=None):
+    """v = D^dagger u (with ``clover``: (D + C)^dagger u = D^dagger u + C u)."""
+    return _apply("dirac_apply_dagger", op, gauge, u, mass, antiperiodic_t, out, clover)
+
+
+def clover_field(U, csw, antiperiodic_t=True, out=None):
+    """Packed clover field of C = -(c_SW/2) sum sigma F (Eq. def_clov) from U: (Nt,Nz,Ny,Nx,8 Nc^2) real,
+    float64 for complex128 links and float32 for complex64 links."""
+    _require(U, "U")
+    if U.dim() != 7 or U.shape[4] != 4 or U.shape[5] != U.shape[6]:
+        raise ValueError(f"U shape {tuple(U.shape)} is not (Nt,Nz,Ny,Nx,4,Nc,Nc)")
+    prec = {torch.complex128: L.FP64, torch.complex64: L.FP32}.get(U.dtype)
+    if prec is None:
+        raise TypeError("U must be complex128 or complex64")
+    nt, nz, ny, nx, _, nc, _ = U.shape
+    want = (nt, nz, ny, nx, 8 * nc * nc)
+    if out is None:
+        out = torch.empty(want, dtype=_clover_dtype(prec), device=U.device)
+    else:
+        _require(out, "out", U.device)
+        if tuple(out.shape) != want or out.dtype != _clover_dtype(prec):
+            raise ValueError(f"out must be a {want} tensor of {_clover_dtype(prec)}")
+    d = L.Dims()
+    for i, n in enumerate((nx, ny, nz, nt)):
+        d.n[i] = n
+    d.antiperiodic_t = 1 if antiperiodic_t else 0
+    L.check(L.load().dirac_clover_field(prec, _ptr(U), float(csw), _ptr(out), nc, C.byref(d), _stream()),
+            "dirac_clover_field")
+    return out
 
 
 def apply_normal(op, gauge, u, mass, antiperiodic_t=True, out=None, tmp=None):
@@ -358,7 +412,8 @@ class SolveInfo:
     betas: list
 
 
-def _solve(fn, solver, op, gauge, b, mass, x0, tol, maxit, inner, gauge_lo, antiperiodic_t, history, opts):
+def _solve(fn, solver, op, gauge, b, mass, x0, tol, maxit, inner, gauge_lo, antiperiodic_t, history, opts,
+           clover=None, clover_lo=None):
     _require(b, "b")
     g = geometry(op, b, antiperiodic_t)
     _check_gauge(g, gauge, device=b.device)
@@ -395,6 +450,15 @@ def _solve(fn, solver, op, gauge, b, mass, x0, tol, maxit, inner, gauge_lo, anti
     o = L.SolveOpts()
     for k, v in (opts or {}).items():
         setattr(o, k, v)
+    if clover is not None:
+        _check_clover(g, clover, device=b.device)
+        o.clover_hi = _ptr(clover)
+        if inner_p != outer:
+            if clover_lo is None:
+                raise ValueError("a mixed solve with a clover term needs clover_lo (float32)")
+            _check_clover(Geometry(g.op, inner_p, g.nc, g.nv, g.dims, g.antiperiodic_t), clover_lo, "clover_lo",
+                          b.device)
+            o.clover_lo = _ptr(clover_lo)
     status = getattr(lib, fn)(g.op, outer, inner_p, _ptr(gauge), _ptr(gauge_lo) if gauge_lo is not None else None,
                               _ptr(b), _ptr(x), float(mass), g.nc, g.nv, C.byref(d), float(tol), int(maxit), _ptr(ws),
                               nbytes, C.byref(info), C.byref(o), _stream())
@@ -407,16 +471,18 @@ def _solve(fn, solver, op, gauge, b, mass, x0, tol, maxit, inner, gauge_lo, anti
 
 
 def cg(op, gauge, b, mass, x0=None, tol=1e-10, maxit=1000, inner=None, gauge_lo=None, antiperiodic_t=True,
-       history=False, opts=None):
-    """Solve D^dagger D x = b by CG (N_v RHS in lock-step).  inner="fp32"/"bf16" for mixed precision."""
-    return _solve("cg_solve", 0, op, gauge, b, mass, x0, tol, maxit, inner, gauge_lo, antiperiodic_t, history, opts)
+       history=False, opts=None, clover=None, clover_lo=None):
+    """Solve D^dagger D x = b by CG (N_v RHS in lock-step; D x = b for the hermitian Laplacians).
+    inner="fp32"/"bf16" for mixed precision; clover (and clover_lo when mixed) for D + C."""
+    return _solve("cg_solve", 0, op, gauge, b, mass, x0, tol, maxit, inner, gauge_lo, antiperiodic_t, history, opts,
+                  clover, clover_lo)
 
 
 def bicgstab(op, gauge, b, mass, x0=None, tol=1e-10, maxit=1000, inner=None, gauge_lo=None, antiperiodic_t=True,
-             opts=None):
+             opts=None, clover=None, clover_lo=None):
     """Solve D x = b by BiCGstab (Wilson, Brillouin).  inner="fp32"/"bf16" for defect-correction mixed precision."""
     return _solve("bicgstab_solve", 1, op, gauge, b, mass, x0, tol, maxit, inner, gauge_lo, antiperiodic_t, False,
-                  opts)
+                  opts, clover, clover_lo)
 
 
 def probe_copy(src: torch.Tensor, dst: torch.Tensor, reps: int = 10) -> float:
@@ -446,9 +512,8 @@ def flops_per_site(op, nc: int) -> float:
 
 
 def set_launch_shape(op, prec, rb: int = 0, variant: int = 0):
-    """Launch-shape knob of the stencil kernels: RHS per thread (0 = automatic) and variant
-    (0 = automatic, 1 = direct global loads, 2 = LDS-staged site tiles, 3 = direct loads one hop per
-    iteration, 4..8 = row tiles (8: Wilson with links staged in LDS); see include/dirac.h)."""
+    """Launch-shape knob of the stencil kernels: RHS columns per thread (0 = automatic) and variant
+    (0 = automatic, 1 = direct global loads, 4 = row tiles staged in LDS; see include/dirac.h)."""
     if isinstance(prec, str):
         prec = {"fp64": L.FP64, "fp32": L.FP32, "bf16": L.BF16}[prec]
     L.check(L.load().dirac_set_launch_shape(_op(op), prec, rb, variant), "set_launch_shape")

@@ -45,6 +45,43 @@ def col_rel_err(v: np.ndarray, ref: np.ndarray) -> float:
     return float(np.max(num / np.maximum(den, 1e-300)))
 
 
+def elem_rel_err(v: np.ndarray, ref: np.ndarray) -> float:
+    """max |v - ref| over every element / max |ref|: a localized error is not diluted by the column norm."""
+    return float(np.max(np.abs(v - ref)) / max(float(np.max(np.abs(ref))), 1e-300))
+
+
+def parity(v: np.ndarray, ref: np.ndarray, tol: float, what=""):
+    """Both bars: worst RHS column 2-norm error and element-wise max error, each relative, below tol."""
+    ce, ee = col_rel_err(v, ref), elem_rel_err(v, ref)
+    assert ce < tol and ee < tol, (what, "column", ce, "element", ee, "tol", tol)
+    return ce, ee
+
+
+def unpack_clover(packed: np.ndarray, nc: int) -> np.ndarray:
+    """Packed clover blocks (..., 8 nc^2) -> (..., 4 nc, 4 nc) matrices indexed (colour, spin) as the
+    vector layout: block h holds spins 2h, 2h+1; within a block component i is spin 2h + i // nc, colour
+    i % nc; N = 2 nc diagonal reals, then (re, im) of (i, j), i < j, row by row."""
+    n = 2 * nc
+    lead = packed.shape[:-1]
+    out = np.zeros(lead + (4 * nc, 4 * nc), dtype=np.complex128)
+    for h in range(2):
+        b = packed[..., h * n * n:(h + 1) * n * n].astype(np.float64)
+        blk = np.zeros(lead + (n, n), dtype=np.complex128)
+        for i in range(n):
+            blk[..., i, i] = b[..., i]
+        e = n
+        for i in range(n):
+            for j in range(i + 1, n):
+                blk[..., i, j] = b[..., e] + 1j * b[..., e + 1]
+                blk[..., j, i] = b[..., e] - 1j * b[..., e + 1]
+                e += 2
+        idx = [(i % nc) * 4 + 2 * h + i // nc for i in range(n)]
+        for i in range(n):
+            for j in range(n):
+                out[..., idx[i], idx[j]] = blk[..., i, j]
+    return out
+
+
 def sample_sites(dims, count, seed=123, include_boundary=True):
     """Random site coordinates (x,y,z,t), plus sites on the t = 0 and t = Nt-1 slices."""
     rng = np.random.default_rng(seed)

@@ -1,21 +1,23 @@
 """GPU parity of the stencil applies (Wilson, Brillouin, staggered, their adjoints) against the oracle.
 
-Bars: FP64 1e-12 and FP32 1e-5 relative (per-RHS column 2-norm, worst column), with the
-oracle evaluated in FP64 on the same rounded inputs; BF16 storage is reported and held to a
-sanity bound of 2e-2 (bfloat16 keeps 8 significant bits).
+Bars: FP64 1e-12 and FP32 1e-5 relative, each on two metrics (the worst per-RHS column 2-norm error
+and the element-wise max error over max |ref|, so that a localized error is not diluted), with the
+oracle evaluated in FP64 on the same rounded inputs; BF16 storage is reported and held to a sanity
+bound of 2e-2 (bfloat16 keeps 8 significant bits).
 """
 import numpy as np
 import pytest
 import torch
 
 import synthetic_inputs as si
-from oracle.brillouin import brillouin_apply, brillouin_apply_dagger, brillouin_links, brillouin_links_all
+from oracle.brillouin import (brillouin_apply, brillouin_apply_dagger, brillouin_apply_sites, brillouin_links,
+                              brillouin_links_all)
 from oracle.dense import wilson_dense
 from oracle.staggered import staggered_apply, staggered_apply_dagger
 from oracle.wilson import free_wilson_symbol, wilson_apply, wilson_apply_dagger
 from paper_2112_14640_amd import dirac
-from tests.gpu_helpers import (at_sites, bf16_pairs_to_host, col_rel_err, host, round_bf16, round_c64, sample_sites,
-                               to_bf16_pairs, to_dev)
+from tests.gpu_helpers import (at_sites, bf16_pairs_to_host, col_rel_err, host, parity, round_bf16, round_c64,
+                               sample_sites, to_bf16_pairs, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -70,7 +72,7 @@ def test_wilson_4x4_dense_fp64():
     cols = u.reshape(-1, 1)
     for dagger, mat in ((False, d), (True, d.conj().T)):
         v, _, _ = _run("wilson", "fp64", U, u, cfg["mass"], True, dagger)
-        assert col_rel_err(v, (mat @ cols).reshape(u.shape)) < 1e-12
+        parity(v, (mat @ cols).reshape(u.shape), 1e-12, dagger)
 
 
 SMALL = [
@@ -92,32 +94,37 @@ def test_small_lattice_parity(op, prec, case):
     for dagger in (False, True):
         v, g_in, u_in = _run(op, prec, gauge, u, 0.07, apbc, dagger)
         ref = ORACLE[(op, dagger)](g_in, u_in, 0.07, apbc)
-        err = col_rel_err(v, ref)
-        assert err < TOL[prec], (op, prec, dims, nc, nv, dagger, err)
+        parity(v, ref, TOL[prec], (op, prec, dims, nc, nv, dagger))
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("op", ["wilson", "staggered", "brillouin"])
-def test_apply_16x32_nv12_fp32_sampled(op):
-    """Config 16^3x32, Nc=3, Nv=12, FP32, links exp(i 0.3 H), m=0.05: ~1000 sampled output sites + t boundaries."""
+def test_apply_16x32_nv12_sampled(op, prec):
+    """Config 16^3x32, Nc=3, Nv=12, links exp(i 0.3 H), m=0.05: ~1000 sampled output sites + t boundaries.
+    Brillouin runs on the links W the GPU builds from U; the oracle forms all 81 W_d at the sampled
+    sites from the same (FP32-rounded) U."""
     cfg = si.config("apply_16x32")
     rng = np.random.default_rng(cfg["seed"])
     dims, nc, nv, m = cfg["dims"], cfg["nc"], cfg["nv"], cfg["mass"]
     U = si.gauge_field(rng, dims, nc, "near", cfg["spread"])
-    if op == "brillouin":
-        nx, ny, nz, nt = dims
-        # the apply is defined for any stored links; near-identity SU(3) stand-ins keep the test fast
-        gauge = si.near_identity_su_n(rng, (nt, nz, ny, nx, 40), nc, 0.3)
-        u = si.wilson_vector(rng, dims, nc, nv)
-    elif op == "staggered":
-        gauge, u = U, si.staggered_vector(rng, dims, nc, nv)
-    else:
-        gauge, u = U, si.wilson_vector(rng, dims, nc, nv)
+    u = si.staggered_vector(rng, dims, nc, nv) if op == "staggered" else si.wilson_vector(rng, dims, nc, nv)
     sites = sample_sites(dims, 1000)
+    if prec == "fp32":
+        ud, u_in = to_dev(u, torch.complex64), round_c64(u)
+    else:
+        ud, u_in = to_bf16_pairs(u), round_bf16(u)
+    U32 = to_dev(U, torch.complex64)
+    gauge = dirac.brillouin_links(U32) if op == "brillouin" else U32
+    W81 = brillouin_links_all(round_c64(U), sites=sites) if op == "brillouin" else None
     for dagger in (False, True):
-        v, g_in, u_in = _run(op, "fp32", gauge, u, m, True, dagger)
-        ref = ORACLE[(op, dagger)](g_in, u_in, m, True, sites=sites)
-        err = col_rel_err(at_sites(v, sites), ref)
-        assert err < 1e-5, (op, dagger, err)
+        fn = dirac.apply_dagger if dagger else dirac.apply
+        v = fn(op, gauge, ud, m)
+        vh = bf16_pairs_to_host(v) if prec == "bf16" else host(v).astype(np.complex128)
+        if op == "brillouin":
+            ref = brillouin_apply_sites(W81, u_in, m, sites, True, dagger)
+        else:
+            ref = ORACLE[(op, dagger)](round_c64(U), u_in, m, True, sites=sites)
+        parity(at_sites(vh, sites), ref, 1e-5 if prec == "fp32" else TOL["bf16"], (op, prec, dagger))
 
 
 def test_brillouin_links_parity():
@@ -154,7 +161,7 @@ def test_gamma5_hermiticity_16x32(op):
     u = to_dev(si.wilson_vector(rng, dims, nc, nv), torch.complex64)
     lhs = dirac.apply_dagger(op, gauge, u, 0.05)
     rhs = dirac.gamma5(op, dirac.apply(op, gauge, dirac.gamma5(op, u), 0.05))
-    assert col_rel_err(host(lhs), host(rhs)) < 1e-6
+    parity(host(lhs), host(rhs), 1e-6, op)
 
 
 def test_staggered_epsilon_hermiticity_16x32():
@@ -165,7 +172,7 @@ def test_staggered_epsilon_hermiticity_16x32():
     u = to_dev(si.staggered_vector(rng, dims, nc, nv), torch.complex64)
     lhs = dirac.apply_dagger("staggered", U, u, 0.05)
     rhs = dirac.gamma5("staggered", dirac.apply("staggered", U, dirac.gamma5("staggered", u), 0.05))
-    assert col_rel_err(host(lhs), host(rhs)) < 1e-6
+    parity(host(lhs), host(rhs), 1e-6)
 
 
 def test_free_field_plane_wave_16x32():
@@ -181,16 +188,24 @@ def test_free_field_plane_wave_16x32():
     psi = ph[..., None, None, None] * chi
     expect = ph[..., None, None, None] * np.einsum("st,atr->asr", free_wilson_symbol(p, 0.05), chi)
     v = dirac.apply("wilson", to_dev(U), to_dev(psi), 0.05)
-    assert col_rel_err(host(v), expect) < 1e-12
+    parity(host(v), expect, 1e-12)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8])
+# right-hand sides per thread instantiated for each operator; every other rb is refused
+RB_OF = {"wilson": (1, 2), "staggered": (1, 2, 4), "brillouin": (1,)}
+
+
+@pytest.mark.parametrize("variant", [0, 1, 4])
 @pytest.mark.parametrize("rb", [1, 2, 4])
 @pytest.mark.parametrize("op", ["wilson", "staggered", "brillouin"])
 def test_launch_shapes_agree(op, rb, variant):
-    """Every launch shape (RHS per thread, LDS-staged or direct) gives the oracle's result."""
-    if op == "brillouin" and (rb == 4 or variant >= 2):
-        pytest.skip("Brillouin instantiates 1 or 2 right-hand sides per thread and has no tiled variant")
+    """Every launch shape (RHS per thread, row tiles or direct loads) gives the oracle's result; a shape
+    that is not instantiated is refused."""
+    if rb not in RB_OF[op]:
+        with pytest.raises(Exception):
+            dirac.set_launch_shape(op, "fp32", rb, variant)
+        dirac.set_launch_shape(op, "fp32", 0, 0)
+        return
     dims, nc, nv = (6, 4, 4, 6), 3, 12
     gauge, u = _inputs(op, dims, nc, nv, seed=9)
     try:
@@ -199,7 +214,7 @@ def test_launch_shapes_agree(op, rb, variant):
     finally:
         dirac.set_launch_shape(op, "fp32", 0, 0)
     ref = ORACLE[(op, False)](g_in, u_in, 0.1, True)
-    assert col_rel_err(v, ref) < 1e-5
+    parity(v, ref, 1e-5, (op, rb, variant))
 
 
 ROW_CASES = [
@@ -216,22 +231,21 @@ ROW_CASES = [
 ]
 
 
-@pytest.mark.parametrize("variant", [4, 5, 6, 7, 8])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 @pytest.mark.parametrize("case", range(len(ROW_CASES)))
-def test_wilson_row_tiles(case, prec, variant):
-    """The row-tiled Wilson kernel (every rows-per-tile choice, 1 and 2 RHS per thread) against the oracle."""
+def test_wilson_row_tiles(case, prec):
+    """The row-tiled Wilson kernel (1 and 2 RHS per thread; links staged in LDS at Nv = 12) against the
+    oracle."""
     dims, nc, nv, apbc = ROW_CASES[case]
     gauge, u = _inputs("wilson", dims, nc, nv, seed=40 + case)
     for rb in (1, 2):
         if nv % rb:
             continue
         try:
-            dirac.set_launch_shape("wilson", prec, rb, variant)
+            dirac.set_launch_shape("wilson", prec, rb, 4)
             for dagger in (False, True):
                 v, g_in, u_in = _run("wilson", prec, gauge, u, 0.03, apbc, dagger)
-                err = col_rel_err(v, ORACLE[("wilson", dagger)](g_in, u_in, 0.03, apbc))
-                assert err < TOL[prec], (dims, nc, nv, rb, dagger, err)
+                parity(v, ORACLE[("wilson", dagger)](g_in, u_in, 0.03, apbc), TOL[prec], (dims, nc, nv, rb, dagger))
         finally:
             dirac.set_launch_shape("wilson", prec, 0, 0)
 
@@ -254,15 +268,15 @@ BRILLOUIN_ROW_CASES = [
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 @pytest.mark.parametrize("case", range(len(BRILLOUIN_ROW_CASES)))
 def test_brillouin_row_tiles(case, prec):
-    """The row-tiled Brillouin kernel (27 row copies with link windows in LDS) against the oracle."""
+    """The row-tiled Brillouin kernel (27 row copies with link windows in LDS, one RHS per thread, the
+    only instantiated shape) against the oracle."""
     dims, nc, nv, apbc = BRILLOUIN_ROW_CASES[case]
     gauge, u = _inputs("brillouin", dims, nc, nv, seed=60 + case)
     try:
         dirac.set_launch_shape("brillouin", prec, 1, 4)
         for dagger in (False, True):
             v, g_in, u_in = _run("brillouin", prec, gauge, u, 0.04, apbc, dagger)
-            err = col_rel_err(v, ORACLE[("brillouin", dagger)](g_in, u_in, 0.04, apbc))
-            assert err < TOL[prec], (dims, nc, nv, dagger, err)
+            parity(v, ORACLE[("brillouin", dagger)](g_in, u_in, 0.04, apbc), TOL[prec], (dims, nc, nv, dagger))
     finally:
         dirac.set_launch_shape("brillouin", prec, 0, 0)
 
@@ -277,21 +291,22 @@ STAGGERED_ROW_CASES = [
 ]
 
 
-@pytest.mark.parametrize("variant", [4, 8])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 @pytest.mark.parametrize("case", range(len(STAGGERED_ROW_CASES)))
-def test_staggered_row_tiles(case, prec, variant):
-    """The row-tiled staggered kernel (1 and 2 RHS per thread, where a row fits; links loaded per
-    thread (4) or staged in LDS (8)) against the oracle."""
+def test_staggered_row_tiles(case, prec):
+    """The row-tiled staggered kernel (1, 2 and 4 RHS per thread, where a row fits; links staged in LDS
+    in FP32/BF16, loaded per thread in FP64) against the oracle."""
     dims, nc, nv, apbc = STAGGERED_ROW_CASES[case]
     gauge, u = _inputs("staggered", dims, nc, nv, seed=80 + case)
-    for rb in (1, 2):
+    for rb in (1, 2, 4):
+        if nv % rb:
+            continue
         try:
-            dirac.set_launch_shape("staggered", prec, rb, variant)
+            dirac.set_launch_shape("staggered", prec, rb, 4)
             for dagger in (False, True):
                 v, g_in, u_in = _run("staggered", prec, gauge, u, 0.06, apbc, dagger)
-                err = col_rel_err(v, ORACLE[("staggered", dagger)](g_in, u_in, 0.06, apbc))
-                assert err < TOL[prec], (dims, nc, nv, rb, dagger, err)
+                parity(v, ORACLE[("staggered", dagger)](g_in, u_in, 0.06, apbc), TOL[prec],
+                       (dims, nc, nv, rb, dagger))
         finally:
             dirac.set_launch_shape("staggered", prec, 0, 0)
 

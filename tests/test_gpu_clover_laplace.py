@@ -1,0 +1,243 @@
+"""GPU parity of the clover term (Sec. 4, Eq. def_clov) and of the Wilson and Brillouin Laplacians
+(Eqs. app_wlap, app_blap) against the oracle, and their solves.
+
+Bars as for the Dirac applies: FP64 1e-12, FP32 1e-5, BF16 2e-2, on the worst column 2-norm error and
+on the element-wise max error (both relative).  The clover field is compared entry by entry with the
+oracle's per-site 4Nc x 4Nc matrix after unpacking the documented packed layout.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synthetic_inputs as si
+from oracle.brillouin import brillouin_apply, brillouin_apply_dagger, brillouin_links
+from oracle.clover import clover_apply, clover_site_matrix, field_strength
+from oracle.laplace import brillouin_laplace_apply, wilson_laplace_apply
+from oracle.wilson import wilson_apply, wilson_apply_dagger
+from paper_2112_14640_amd import dirac
+from tests.gpu_helpers import (at_sites, bf16_pairs_to_host, host, parity, round_bf16, round_c64, sample_sites,
+                               to_bf16_pairs, to_dev, unpack_clover)
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16": 2e-2}
+DIRAC = {("wilson", False): wilson_apply, ("wilson", True): wilson_apply_dagger,
+         ("brillouin", False): brillouin_apply, ("brillouin", True): brillouin_apply_dagger}
+LAPLACE = {"wilson_laplace": wilson_laplace_apply, "brillouin_laplace": brillouin_laplace_apply}
+
+CASES = [
+    # dims, nc, nv, antiperiodic: row tiles, a ragged direct launch, several colour counts
+    ((6, 4, 4, 6), 3, 12, True),
+    ((4, 6, 2, 8), 3, 3, True),
+    ((4, 2, 6, 4), 2, 4, False),
+    ((2, 2, 2, 2), 4, 2, True),
+    ((8, 2, 2, 4), 1, 8, True),
+]
+
+
+def _vec(u, prec):
+    """Device vector in `prec` and the values the oracle sees."""
+    if prec == "fp64":
+        return to_dev(u), u
+    if prec == "fp32":
+        return to_dev(u, torch.complex64), round_c64(u)
+    return to_bf16_pairs(u), round_bf16(u)
+
+
+def _links(U, prec):
+    return (to_dev(U), U) if prec == "fp64" else (to_dev(U, torch.complex64), round_c64(U))
+
+
+def _host(v, prec):
+    return bf16_pairs_to_host(v) if prec == "bf16" else host(v).astype(np.complex128)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("nc", [1, 2, 3, 4])
+def test_clover_field_matches_oracle(nc, prec):
+    dims, csw = (4, 6, 4, 6), 1.3
+    rng = np.random.default_rng(200 + nc)
+    U = si.gauge_field(rng, dims, nc, "near", 0.6)
+    Ud, Uo = _links(U, prec)
+    C = dirac.clover_field(Ud, csw)
+    assert C.shape == (6, 4, 6, 4, 8 * nc * nc)
+    got = unpack_clover(host(C), nc)
+    F = field_strength(Uo)
+    ref = np.stack([clover_site_matrix(F[idx], csw) for idx in np.ndindex(*F.shape[:4])]).reshape(got.shape)
+    tol = 1e-13 if prec == "fp64" else 1e-6
+    assert np.max(np.abs(got - ref)) < tol * max(1.0, np.max(np.abs(ref)))
+    if nc > 1:
+        assert np.max(np.abs(ref)) > 1e-2
+
+
+@pytest.mark.parametrize("variant", [1, 4])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("op", ["wilson", "brillouin"])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_clover_apply_small(case, op, prec, variant):
+    """(D + C) u and (D + C)^dagger u = D^dagger u + C u on the row-tile and direct kernels."""
+    dims, nc, nv, apbc = CASES[case]
+    rng = np.random.default_rng(300 + case)
+    U = si.gauge_field(rng, dims, nc, "haar")
+    u = si.wilson_vector(rng, dims, nc, nv)
+    m, csw = 0.08, 1.0
+    Ud, Uo = _links(U, prec)
+    C = dirac.clover_field(Ud, csw)
+    if op == "brillouin":
+        W = brillouin_links(Uo)
+        gauge, g_in = (to_dev(W) if prec == "fp64" else to_dev(W, torch.complex64)), W
+    else:
+        gauge, g_in = Ud, Uo
+    ud, u_in = _vec(u, prec)
+    F = field_strength(Uo)
+    try:
+        dirac.set_launch_shape(op, prec, 0, variant)
+        for dagger in (False, True):
+            fn = dirac.apply_dagger if dagger else dirac.apply
+            v = _host(fn(op, gauge, ud, m, antiperiodic_t=apbc, clover=C), prec)
+            ref = DIRAC[(op, dagger)](g_in, u_in, m, apbc) + clover_apply(F, u_in, csw)
+            parity(v, ref, TOL[prec], (op, prec, dims, nc, nv, dagger, variant))
+    finally:
+        dirac.set_launch_shape(op, prec, 0, 0)
+
+
+@pytest.mark.parametrize("op", ["wilson", "brillouin"])
+def test_clover_apply_16x32_sampled(op):
+    """16^3x32, Nc=3, Nv=12, FP32, links exp(i 0.3 H), m=0.05, c_SW=1 at ~1000 sampled sites."""
+    cfg = si.config("apply_16x32")
+    rng = np.random.default_rng(cfg["seed"])
+    dims, nc, nv, m = cfg["dims"], cfg["nc"], cfg["nv"], cfg["mass"]
+    U = si.gauge_field(rng, dims, nc, "near", cfg["spread"])
+    u = si.wilson_vector(rng, dims, nc, nv)
+    U32 = to_dev(U, torch.complex64)
+    C = dirac.clover_field(U32, 1.0)
+    sites = sample_sites(dims, 1000)
+    Uo, u_in = round_c64(U), round_c64(u)
+    F = field_strength(Uo)
+    if op == "brillouin":
+        from oracle.brillouin import brillouin_apply_sites, brillouin_links_all
+
+        gauge = dirac.brillouin_links(U32)
+        W81 = brillouin_links_all(Uo, sites=sites)
+    else:
+        gauge = U32
+    ud = to_dev(u, torch.complex64)
+    for dagger in (False, True):
+        fn = dirac.apply_dagger if dagger else dirac.apply
+        v = at_sites(host(fn(op, gauge, ud, m, clover=C)).astype(np.complex128), sites)
+        if op == "brillouin":
+            ref = brillouin_apply_sites(W81, u_in, m, sites, True, dagger)
+        else:
+            ref = DIRAC[(op, dagger)](Uo, u_in, m, True, sites=sites)
+        ref = ref + clover_apply(F, u_in, 1.0, sites=sites)
+        parity(v, ref, 1e-5, (op, dagger))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("op", ["wilson_laplace", "brillouin_laplace"])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_laplace_apply_small(case, op, prec):
+    """The Laplacians on every instantiated launch shape (row tiles and direct; the Wilson Laplacian
+    with 1, 2 and 4 columns per thread), and D^dagger = D."""
+    dims, nc, nv, apbc = CASES[case]
+    rng = np.random.default_rng(400 + case)
+    U = si.gauge_field(rng, dims, nc, "haar")
+    u = si.wilson_vector(rng, dims, nc, nv)
+    m = 0.3
+    Ud, Uo = _links(U, prec)
+    if op == "brillouin_laplace":
+        W = brillouin_links(Uo)
+        gauge, g_in = (to_dev(W) if prec == "fp64" else to_dev(W, torch.complex64)), W
+    else:
+        gauge, g_in = Ud, Uo
+    ud, u_in = _vec(u, prec)
+    ref = LAPLACE[op](g_in, u_in, m, apbc)
+    shapes = [(rb, var) for rb in (1, 2, 4) for var in (1, 4)] if op == "wilson_laplace" else [(1, 1), (1, 4)]
+    try:
+        for rb, var in shapes:
+            dirac.set_launch_shape(op, prec, rb, var)
+            for dagger in (False, True):
+                fn = dirac.apply_dagger if dagger else dirac.apply
+                v = _host(fn(op, gauge, ud, m, antiperiodic_t=apbc), prec)
+                parity(v, ref, TOL[prec], (op, prec, dims, nc, nv, rb, var, dagger))
+    finally:
+        dirac.set_launch_shape(op, prec, 0, 0)
+
+
+@pytest.mark.parametrize("op", ["wilson_laplace", "brillouin_laplace"])
+def test_laplace_16x32_sampled(op):
+    cfg = si.config("apply_16x32")
+    rng = np.random.default_rng(cfg["seed"] + 1)
+    dims, nc, nv, m = cfg["dims"], cfg["nc"], cfg["nv"], cfg["mass"]
+    U = si.gauge_field(rng, dims, nc, "near", cfg["spread"])
+    u = si.wilson_vector(rng, dims, nc, nv)
+    U32 = to_dev(U, torch.complex64)
+    sites = sample_sites(dims, 600)
+    Uo, u_in = round_c64(U), round_c64(u)
+    v = at_sites(host(dirac.apply(op, dirac.brillouin_links(U32) if op == "brillouin_laplace" else U32,
+                                  to_dev(u, torch.complex64), m)).astype(np.complex128), sites)
+    if op == "brillouin_laplace":
+        ref = LAPLACE[op](brillouin_links(Uo), u_in, m, True, sites=sites)
+    else:
+        ref = LAPLACE[op](Uo, u_in, m, True, sites=sites)
+    parity(v, ref, 1e-5, op)
+
+
+def _colres(r, b):
+    return np.linalg.norm(r.reshape(-1, r.shape[-1]), axis=0) / np.linalg.norm(b.reshape(-1, b.shape[-1]), axis=0)
+
+
+@pytest.mark.parametrize("inner", [None, "fp32", "bf16"])
+@pytest.mark.parametrize("op", ["wilson_laplace", "brillouin_laplace"])
+def test_laplace_cg(op, inner):
+    """CG on the hermitian positive definite Laplacians (Sec. 9: A = -Delta/2 + m^2/2), plain and mixed;
+    the oracle recomputes the FP64 residual."""
+    dims, nc, nv, m = (4, 4, 4, 8), 3, 3, 0.01
+    rng = np.random.default_rng(500)
+    U = si.gauge_field(rng, dims, nc, "near", 0.5)
+    b = si.wilson_vector(rng, dims, nc, nv)
+    gauge = brillouin_links(U) if op == "brillouin_laplace" else U
+    gd = to_dev(gauge)
+    kw = {} if inner is None else dict(inner=inner, gauge_lo=gd.to(torch.complex64))
+    x, info = dirac.cg(op, gd, to_dev(b), m, tol=1e-10, maxit=4000, **kw)
+    assert info.reason == "converged", info
+    res = _colres(b - LAPLACE[op](gauge, host(x), m), b)
+    assert np.all(res < 1e-10), res
+
+
+@pytest.mark.parametrize("solver,inner", [("cg", None), ("cg", "fp32"), ("cg", "bf16"), ("bicgstab", None),
+                                          ("bicgstab", "fp32")])
+@pytest.mark.parametrize("op", ["wilson", "brillouin"])
+def test_clover_solves(op, solver, inner):
+    """CG on (D + C)^dagger (D + C) and BiCGstab on D + C with c_SW = 1 (the paper's solver setting),
+    plain FP64 and mixed; the oracle recomputes the FP64 residual."""
+    dims, nc, nv, m, csw = (4, 4, 4, 8), 3, 3, 0.05, 1.0
+    rng = np.random.default_rng(510)
+    U = si.gauge_field(rng, dims, nc, "near", 0.5)
+    b = si.wilson_vector(rng, dims, nc, nv)
+    F = field_strength(U)
+    gauge = brillouin_links(U) if op == "brillouin" else U
+    gd = to_dev(gauge)
+    C64 = dirac.clover_field(to_dev(U), csw)
+    kw = dict(clover=C64)
+    if inner is not None:
+        kw.update(inner=inner, gauge_lo=gd.to(torch.complex64), clover_lo=dirac.clover_field(to_dev(U, torch.complex64),
+                                                                                                csw))
+    dfn = DIRAC[(op, False)]
+    dd = DIRAC[(op, True)]
+
+    def D(x):
+        return dfn(gauge, x, m) + clover_apply(F, x, csw)
+
+    def Dd(x):
+        return dd(gauge, x, m) + clover_apply(F, x, csw)
+
+    if solver == "cg":
+        x, info = dirac.cg(op, gd, to_dev(b), m, tol=1e-10, maxit=4000, **kw)
+        r = b - Dd(D(host(x)))
+    else:
+        x, info = dirac.bicgstab(op, gd, to_dev(b), m, tol=1e-10, maxit=4000, **kw)
+        r = b - D(host(x))
+    assert info.reason == "converged", info
+    res = _colres(r, b)
+    assert np.all(res < 1e-10), res

@@ -17,7 +17,7 @@ from oracle.brillouin import brillouin_apply_sites, brillouin_links_all
 from oracle.staggered import staggered_apply, staggered_apply_dagger
 from oracle.wilson import wilson_apply, wilson_apply_dagger
 from paper_2112_14640_amd import dirac
-from tests.gpu_helpers import DEV, col_rel_err, host, sample_sites
+from tests.gpu_helpers import DEV, host, parity, sample_sites
 
 pytestmark = pytest.mark.gpu
 
@@ -65,8 +65,7 @@ def test_brillouin_48x96_nv12_fp32_sampled():
     assert np.max(np.abs(w_dev - w81[:, :40])) < 2e-6
     for dag in (False, True):
         ref = brillouin_apply_sites(w81, uh, MASS, sites, True, dagger=dag)
-        err = col_rel_err(got[dag], ref)
-        assert err < 1e-5, (dag, err)
+        parity(got[dag], ref, 1e-5, dag)
     del U, u, Uh, uh
     _free()
 
@@ -80,8 +79,7 @@ def test_staggered_48x96_nv12_fp32_sampled():
            for dag in (False, True)}
     Uh, uh = host(U), host(u)
     for dag, fn in ((False, staggered_apply), (True, staggered_apply_dagger)):
-        err = col_rel_err(got[dag], fn(Uh, uh, MASS, True, sites=sites))
-        assert err < 1e-5, (dag, err)
+        parity(got[dag], fn(Uh, uh, MASS, True, sites=sites), 1e-5, dag)
     del U, u, Uh, uh
     _free()
 
@@ -97,8 +95,7 @@ def test_wilson_32x64_nc_nv_fp32_sampled(nc, nv):
            for dag in (False, True)}
     Uh, uh = host(U), host(u)
     for dag, fn in ((False, wilson_apply), (True, wilson_apply_dagger)):
-        err = col_rel_err(got[dag], fn(Uh, uh, MASS, True, sites=sites))
-        assert err < 1e-5, (nc, nv, dag, err)
+        parity(got[dag], fn(Uh, uh, MASS, True, sites=sites), 1e-5, (nc, nv, dag))
     del U, u, Uh, uh
     _free()
 
@@ -122,7 +119,7 @@ def test_bicgstab_brillouin_32x64_mixed_to_1e8():
     _free()
     w81 = brillouin_links_all(host(U64), sites=sites)
     dx_ref = brillouin_apply_sites(w81, host(x), MASS, sites, True)
-    assert col_rel_err(dx_dev, dx_ref) < 1e-12
+    parity(dx_dev, dx_ref, 1e-12)
     # residual at the sampled sites against b there: of the size of the global relative residual
     res = np.linalg.norm((b_s - dx_ref).reshape(-1, 12), axis=0) / np.linalg.norm(b_s.reshape(-1, 12), axis=0)
     assert np.all(res < 1e-6), res
