@@ -181,6 +181,15 @@ int dirac_norm2(dirac_prec prec, const void* x, int64_t nrows, int nv, double* o
                 void* stream);
 int dirac_dot(dirac_prec prec_x, const void* x, dirac_prec prec_y, const void* y, int64_t nrows, int nv, double* out,
               void* workspace, size_t ws_bytes, void* stream);
+/* dirac_dot without a workspace argument, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  The reduction partials live
+ * in a library-owned device array of 8 MiB (2048 blocks x 2 x 256 doubles) that each GPU the library
+ * runs on holds until the process ends; the call itself allocates nothing.  nv must be in 1..256
+ * (EINVAL beyond).  The array is shared by every call on that GPU: calls that overlap in time on one GPU
+ * (other streams, other threads) race and give wrong results; serialise them.  Same arguments,
+ * results (bit for bit) and errors as dirac_dot otherwise. */
+int dirac_dot_noalloc(dirac_prec prec_x, const void* x, dirac_prec prec_y, const void* y, int64_t nrows, int nv,
+                      double* out, void* stream);
 int dirac_caxpy(dirac_prec prec_x, const void* x, dirac_prec prec_y, void* y, const double* a, int64_t nrows,
                 int nv, void* stream);
 int dirac_cxpay(dirac_prec prec_x, const void* x, dirac_prec prec_y, void* y, const double* a, int64_t nrows,

@@ -67,6 +67,7 @@ SIGNATURES = {
     "dirac_blas_workspace_bytes": (_sz, [_i]),
     "dirac_norm2": (_i, [_i, _vp, _i64, _i, _vp, _vp, _sz, _vp]),
     "dirac_dot": (_i, [_i, _vp, _i, _vp, _i64, _i, _vp, _vp, _sz, _vp]),
+    "dirac_dot_noalloc": (_i, [_i, _vp, _i, _vp, _i64, _i, _vp, _vp]),
     "dirac_caxpy": (_i, [_i, _vp, _i, _vp, _vp, _i64, _i, _vp]),
     "dirac_cxpay": (_i, [_i, _vp, _i, _vp, _vp, _i64, _i, _vp]),
     "dirac_cast": (_i, [_i, _vp, _i, _vp, _i64, _vp]),

@@ -304,6 +304,23 @@ int dirac_dot(dirac_prec prec_x, const void* x, dirac_prec prec_y, const void* y
     return DIRAC_OK;
 }
 
+int dirac_dot_noalloc(dirac_prec prec_x, const void* x, dirac_prec prec_y, const void* y, int64_t nrows, int nv,
+                      double* out, void* stream) {
+    int rc = blas_check(prec_x, nrows, nv);
+    if (!rc) rc = blas_check(prec_y, nrows, nv);
+    if (rc) return rc;
+    if (!x || !y || !out) return fail(DIRAC_EINVAL, "NULL pointer");
+    if (reduce_partial_doubles(nv) > static_scratch_doubles())
+        return fail(DIRAC_EINVAL, "nv beyond the static scratch (at most 256 right-hand sides)");
+    double* partial = nullptr;
+    if ((rc = static_scratch(&partial))) return rc;
+    // every block writes all of its partials before the finalize reads them: nothing to clear
+    rc = blas_dot(prec_x, x, prec_y, y, nrows, nv, partial, out, as_stream(stream));
+    if (rc) return fail(rc, "dot launch rejected");
+    DIRAC_HIP(hipGetLastError());
+    return DIRAC_OK;
+}
+
 int dirac_caxpy(dirac_prec prec_x, const void* x, dirac_prec prec_y, void* y, const double* a, int64_t nrows, int nv,
                 void* stream) {
     int rc = blas_check(prec_x, nrows, nv);

@@ -7,6 +7,8 @@
 // block handles rows blockIdx + k * gridDim in a fixed order and reduces per RHS through
 // LDS in a fixed order, then one block per output value adds the block partials with a
 // fixed tree.  Repeated runs give bitwise identical results.
+#include <mutex>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -543,6 +545,36 @@ int fused_xp_update_dot(dirac_prec px, void* x, dirac_prec pp, void* p, dirac_pr
             });
         });
     });
+}
+
+// ---------------------------------------------------------------------------
+// Reduction partials without a workspace argument, for callers that cannot allocate: a file-scope
+// device array sized for the largest N_v (each device holds its own copy for the life of the process).
+// Host code reaches it only through the address hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kScratchDoubles = static_cast<size_t>(kReduceBlocks) * 2 * 256;  // 8 MiB
+__device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+size_t static_scratch_doubles() { return kScratchDoubles; }
+
+int static_scratch(double** out) {
+    int dev = 0;
+    DIRAC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(DIRAC_EUNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        DIRAC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return DIRAC_OK;
 }
 
 int fused_bicg_xr(dirac_prec p, void* x, const void* pv, const void* s, const void* t, void* r, const double* alpha,

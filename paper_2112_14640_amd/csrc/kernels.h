@@ -58,6 +58,10 @@ constexpr int kReduceThreads = 256;
 inline size_t reduce_partial_doubles(int nv) { return static_cast<size_t>(kReduceBlocks) * 2 * nv; }
 
 int blas_norm2(dirac_prec p, const void* x, int64_t nrows, int nv, double* partial, double* out, hipStream_t st);
+// Device address of the library's own reduction partials on the current device (found once per
+// device); static_scratch_doubles() doubles, enough for reduce_partial_doubles(256).
+int static_scratch(double** out);
+size_t static_scratch_doubles();
 int blas_dot(dirac_prec px, const void* x, dirac_prec py, const void* y, int64_t nrows, int nv, double* partial,
              double* out, hipStream_t st);
 // y += a x  (a: device, 2 nv doubles)
