@@ -16,6 +16,7 @@ but with no blocking, fusion or reordering beyond what the definitions state:
 * ``staggered``  D_S (Eq. def_stag) and its adjoint
 * ``clover``     clover-leaf field strength and the clover term C (Sec. 4, Eq. def_clov)
 * ``laplace``    the embedded Wilson and Brillouin Laplacians -Delta/2 + m^2/2 (Eqs. app_wlap, app_blap)
+* ``stout``      stout smearing of the links (Sec. 2; rho = 0.12, three steps by default)
 * ``dense``      brute-force dense matrices assembled from the operator-level definitions
 * ``solvers``    CG / BiCGstab (Sec. 9) and the CG-Lanczos spectrum estimate
 * ``force``      link gradients ("fermion force") of Dirac bilinears and solves
