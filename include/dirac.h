@@ -146,13 +146,35 @@ int dirac_brillouin_links(dirac_prec prec, const void* U, void* W, int nc, const
  * Link gradient ("fermion force") of the bilinear Re sum_rhs psi^dagger D chi with
  * respect to the gauge field, in the convention g = dL/dRe U + i dL/dIm U:
  *   g += coeff * dRe(psi^+ D chi)/dU.
- * Wilson: g_mu(n) = -1/2 b sum_{s,rhs} [((1-g_mu) psi(n))_s chi_s(n+mu)^+ + chi_s(n) ((1+g_mu) psi(n+mu))_s^+]
- * Staggered: g_mu(n) = 1/2 eta_mu(n) b sum_rhs [psi(n) chi(n+mu)^+ - chi(n) psi(n+mu)^+]
- * (b = boundary sign of the hop).  FP64 only: U, psi, chi, g complex128; g has U's
- * layout and is accumulated into (the caller zeroes it first).  Brillouin: EUNSUPPORTED.
+ * Wilson (from Eq. app_wils, the hops through U_mu(n)):
+ *   g_mu(n) = -1/2 b sum_{s,rhs} [((1-g_mu) psi(n))_s chi_s(n+mu)^+ + chi_s(n) ((1+g_mu) psi(n+mu))_s^+]
+ * Staggered (from Eq. def_stag): g_mu(n) = 1/2 eta_mu(n) b sum_rhs [psi(n) chi(n+mu)^+ - chi(n) psi(n+mu)^+]
+ * Brillouin (from Eq. app_bril; the gradient with respect to the 40 stored links W, `U` is then W and g
+ * has W's layout): g_d(n) = b sum_{s,rhs} [psi(n) (S_d chi(n+d))^+ + (psi(n+d) (S_{-d} chi(n))^+)^+],
+ *   S_d = rho_|d| sum_mu d_mu g_mu - lambda_|d|/2 (W_d(n) also enters the hop n+d -> n as W_{-d}(n+d)^+).
+ * (b = boundary sign of the hop).  FP64 only: U, psi, chi, g complex128; g has the gauge
+ * layout and is accumulated into (the caller zeroes it first).  The clover term's gradient is not provided.
  */
 int dirac_force(dirac_op op, const void* U, const void* psi, const void* chi, void* g, double coeff, int nc,
                 int nv, const dirac_dims* dims, void* stream);
+
+/*
+ * Stout smearing (Sec. 2: the smeared links V of the operators; Morningstar and Peardon), one step:
+ *   C_mu(n) = rho sum_{nu != mu} [U_nu(n) U_mu(n+nu) U_nu(n+mu)^+ + U_nu(n-nu)^+ U_mu(n-nu) U_nu(n-nu+mu)],
+ *   Omega = C U^+, Q = (i/2)(Omega^+ - Omega) - (i/(2Nc)) Tr(Omega^+ - Omega), V_mu(n) = exp(i Q) U_mu(n),
+ * all links from the old field (the paper's default is three steps of rho = 0.12; call once per step).
+ * dirac_stout_backward: gU += dL/dU for L(V(U)) given gV = dL/dV (one step; U is that step's input).
+ * dirac_brillouin_links_backward: gV += dL/dV for L(W(V)) given gW = dL/dW on the 40 stored directions of
+ *   dirac_brillouin_links (Tab. off-axis: path averages of V).
+ * FP64 only: U, V, gU, gV complex128 [s][4][nc][nc]; gW complex128 [s][40][nc][nc].  Outputs must not overlap
+ * the inputs.  The backward calls add with atomics: the summation order, and so the last bits, can vary
+ * from run to run.  Errors: EINVAL, EUNSUPPORTED (nc), EHIP.
+ */
+int dirac_stout_smear(const void* U, void* V, double rho, int nc, const dirac_dims* dims, void* stream);
+int dirac_stout_backward(const void* U, const void* gV, void* gU, double rho, int nc, const dirac_dims* dims,
+                         void* stream);
+int dirac_brillouin_links_backward(const void* V, const void* gW, void* gV, int nc, const dirac_dims* dims,
+                                   void* stream);
 
 /* su(Nc) projection of a link gradient: F = (i/2)(U g^+ - g U^+) minus trace/Nc, so that
  * dL/deps = sum tr(H F) for U -> exp(i eps H) U.  FP64; U, g, F: nlinks Nc x Nc matrices.

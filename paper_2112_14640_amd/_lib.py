@@ -64,6 +64,9 @@ SIGNATURES = {
     "dirac_brillouin_links": (_i, [_i, _vp, _vp, _i, _dims, _vp]),
     "dirac_force": (_i, [_i, _vp, _vp, _vp, _vp, _d, _i, _i, _dims, _vp]),
     "dirac_project_su": (_i, [_vp, _vp, _vp, _i, _i64, _vp]),
+    "dirac_stout_smear": (_i, [_vp, _vp, _d, _i, _dims, _vp]),
+    "dirac_stout_backward": (_i, [_vp, _vp, _vp, _d, _i, _dims, _vp]),
+    "dirac_brillouin_links_backward": (_i, [_vp, _vp, _vp, _i, _dims, _vp]),
     "dirac_blas_workspace_bytes": (_sz, [_i]),
     "dirac_norm2": (_i, [_i, _vp, _i64, _i, _vp, _vp, _sz, _vp]),
     "dirac_dot": (_i, [_i, _vp, _i, _vp, _i64, _i, _vp, _vp, _sz, _vp]),

@@ -8,10 +8,15 @@ grad = dL/dRe + i dL/dIm, so that dL = Re sum conj(grad) * d(tensor).
 * ``DiracSolve``  x = (D^dagger D)^{-1} b by CG.  Backward: lambda = (D^dagger D)^{-1} grad_x
   (the normal operator is hermitian, so the adjoint solve is another CG solve),
   grad_b = lambda, grad_U = -[force(D x, lambda) + force(D lambda, x)].
+* ``BrillouinLinks``  W = brillouin_links(V) (Tab. off-axis).  Backward: the path-product chain rule
+  of the library, grad_V from grad_W.
+* ``StoutSmear``  V = n stout steps of U (Sec. 2).  Backward: one library backward step per smearing
+  step, in reverse, from the saved intermediate fields.
 
-Link gradients are available for Wilson and staggered operators in FP64; for
-Brillouin only the vector gradient is provided (grad_W is not implemented and
-requesting it raises).
+Link gradients are FP64.  For Wilson and staggered they are with respect to U; for Brillouin with
+respect to the stored links W, which ``BrillouinLinks`` and ``StoutSmear`` carry back to V and U, so
+U -> V -> W -> D_B is differentiable end to end.  The Laplace operators and the clover term have no
+link gradient here (requesting one raises).
 """
 from __future__ import annotations
 
@@ -35,8 +40,8 @@ class DiracApply(torch.autograd.Function):
         if ctx.needs_input_grad[1]:
             gu = dirac.apply_dagger(ctx.op, gauge, gv, ctx.mass, ctx.apbc)
         if ctx.needs_input_grad[0]:
-            if ctx.op == "brillouin":
-                raise NotImplementedError("the gradient with respect to the Brillouin links W is not implemented")
+            if ctx.op not in ("wilson", "staggered", "brillouin"):
+                raise NotImplementedError(f"no link gradient for the {ctx.op} operator")
             gU = dirac.force(ctx.op, gauge, gv, u, 1.0, ctx.apbc)
         return gU, gu, None, None, None
 
@@ -63,14 +68,54 @@ class DiracSolve(torch.autograd.Function):
             raise RuntimeError(f"DiracSolve backward: adjoint CG did not converge ({info.reason})")
         gU = None
         if ctx.needs_input_grad[0]:
-            if ctx.op == "brillouin":
-                raise NotImplementedError("the gradient with respect to the Brillouin links W is not implemented")
+            if ctx.op not in ("wilson", "staggered", "brillouin"):
+                raise NotImplementedError(f"no link gradient for the {ctx.op} operator")
             dx = dirac.apply(ctx.op, gauge, x, ctx.mass, ctx.apbc)
             dl = dirac.apply(ctx.op, gauge, lam, ctx.mass, ctx.apbc)
             gU = dirac.force(ctx.op, gauge, dx, lam, -1.0, ctx.apbc)
             dirac.force(ctx.op, gauge, dl, x, -1.0, ctx.apbc, out=gU)
         gb = lam if ctx.needs_input_grad[1] else None
         return gU, gb, None, None, None, None, None, None, None
+
+
+class BrillouinLinks(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, V):
+        ctx.save_for_backward(V)
+        return dirac.brillouin_links(V)
+
+    @staticmethod
+    def backward(ctx, gW):
+        (V,) = ctx.saved_tensors
+        return dirac.brillouin_links_backward(V, gW.contiguous())
+
+
+class StoutSmear(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, U, rho, steps):
+        fields = [U]
+        for _ in range(steps):
+            fields.append(dirac.stout_step(fields[-1], rho))
+        ctx.rho = rho
+        ctx.save_for_backward(*fields[:-1])
+        return fields[-1] if steps else U.clone()
+
+    @staticmethod
+    def backward(ctx, gV):
+        g = gV.contiguous()
+        for U in reversed(ctx.saved_tensors):
+            g = dirac.stout_backward(U, g, ctx.rho)
+        return g, None, None
+
+
+def brillouin_links(V):
+    """Differentiable W = brillouin_links(V) (FP64)."""
+    return BrillouinLinks.apply(V)
+
+
+def stout_smear(U, rho=0.12, steps=3):
+    """Differentiable V = ``steps`` stout steps of U (FP64)."""
+    return StoutSmear.apply(U, rho, steps)
 
 
 def apply(op, gauge, u, mass, antiperiodic_t=True):

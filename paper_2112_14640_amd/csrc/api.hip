@@ -243,14 +243,67 @@ int dirac_force(dirac_op op, const void* U, const void* psi, const void* chi, vo
     Geom g;
     int rc = check_common(op, DIRAC_FP64, nc, nv, dims, g);
     if (rc) return rc;
-    if (op != DIRAC_WILSON && op != DIRAC_STAGGERED)
-        return fail(DIRAC_EUNSUPPORTED, "force is implemented for Wilson and staggered");
+    if (op != DIRAC_WILSON && op != DIRAC_STAGGERED && op != DIRAC_BRILLOUIN)
+        return fail(DIRAC_EUNSUPPORTED, "force is implemented for the Wilson, Brillouin and staggered operators");
     if (!psi || !chi || !gout) return fail(DIRAC_EINVAL, "NULL pointer");
     const size_t vb = static_cast<size_t>(rows_of(op, nc, g)) * nv * 16;
     const size_t gb = gauge_bytes(op, DIRAC_FP64, nc, g);
     if (overlap(psi, vb, gout, gb) || overlap(chi, vb, gout, gb)) return fail(DIRAC_EINVAL, "output overlaps inputs");
     rc = launch_force(op, nc, nv, g, U, psi, chi, gout, coeff, as_stream(stream));
     if (rc) return fail(rc, "force launch rejected");
+    DIRAC_HIP(hipGetLastError());
+    return DIRAC_OK;
+}
+
+// The smearing and link-gradient calls share these checks: FP64 links, extents, no overlap of the
+// output with the inputs.
+static int link_call(const void* in1, bool two_inputs, const void* in2, void* out, int nc, const dirac_dims* dims,
+                     Geom& g) {
+    int rc = check_common(DIRAC_WILSON, DIRAC_FP64, nc, 1, dims, g);
+    if (rc) return rc;
+    if (!in1 || !out || (two_inputs && !in2)) return fail(DIRAC_EINVAL, "NULL pointer");
+    if (!aligned(in1, 16) || !aligned(out, 16) || (in2 && !aligned(in2, 16)))
+        return fail(DIRAC_EINVAL, "misaligned pointer");
+    return DIRAC_OK;
+}
+
+int dirac_stout_smear(const void* U, void* V, double rho, int nc, const dirac_dims* dims, void* stream) {
+    Geom g;
+    int rc = link_call(U, false, nullptr, V, nc, dims, g);
+    if (rc) return rc;
+    if (!std::isfinite(rho)) return fail(DIRAC_EINVAL, "rho is not finite");
+    const size_t b = gauge_bytes(DIRAC_WILSON, DIRAC_FP64, nc, g);
+    if (overlap(U, b, V, b)) return fail(DIRAC_EINVAL, "U and V overlap");
+    rc = launch_stout(nc, g, U, V, rho, as_stream(stream));
+    if (rc) return fail(rc, "stout launch rejected");
+    DIRAC_HIP(hipGetLastError());
+    return DIRAC_OK;
+}
+
+int dirac_stout_backward(const void* U, const void* gV, void* gU, double rho, int nc, const dirac_dims* dims,
+                         void* stream) {
+    Geom g;
+    int rc = link_call(U, true, gV, gU, nc, dims, g);
+    if (rc) return rc;
+    if (!std::isfinite(rho)) return fail(DIRAC_EINVAL, "rho is not finite");
+    const size_t b = gauge_bytes(DIRAC_WILSON, DIRAC_FP64, nc, g);
+    if (overlap(U, b, gU, b) || overlap(gV, b, gU, b)) return fail(DIRAC_EINVAL, "gU overlaps U or gV");
+    rc = launch_stout_backward(nc, g, U, gV, gU, rho, as_stream(stream));
+    if (rc) return fail(rc, "stout backward launch rejected");
+    DIRAC_HIP(hipGetLastError());
+    return DIRAC_OK;
+}
+
+int dirac_brillouin_links_backward(const void* V, const void* gW, void* gV, int nc, const dirac_dims* dims,
+                                   void* stream) {
+    Geom g;
+    int rc = link_call(V, true, gW, gV, nc, dims, g);
+    if (rc) return rc;
+    const size_t bv = gauge_bytes(DIRAC_WILSON, DIRAC_FP64, nc, g);
+    const size_t bw = gauge_bytes(DIRAC_BRILLOUIN, DIRAC_FP64, nc, g);
+    if (overlap(V, bv, gV, bv) || overlap(gW, bw, gV, bv)) return fail(DIRAC_EINVAL, "gV overlaps V or gW");
+    rc = launch_links_backward(nc, g, V, gW, gV, as_stream(stream));
+    if (rc) return fail(rc, "link backward launch rejected");
     DIRAC_HIP(hipGetLastError());
     return DIRAC_OK;
 }

@@ -43,6 +43,9 @@ int launch_stencil(dirac_op op, dirac_prec prec, int nc, int nv, const Geom& g, 
 int launch_force(dirac_op op, int nc, int nv, const Geom& g, const void* U, const void* psi, const void* chi,
                  void* gout, double coeff, hipStream_t st);
 int launch_project_su(int nc, int64_t nlinks, const void* U, const void* g, void* F, hipStream_t st);
+int launch_stout(int nc, const Geom& g, const void* U, void* V, double rho, hipStream_t st);
+int launch_stout_backward(int nc, const Geom& g, const void* U, const void* gV, void* gU, double rho, hipStream_t st);
+int launch_links_backward(int nc, const Geom& g, const void* V, const void* gW, void* gV, hipStream_t st);
 
 // RHS-per-thread choice for a stencil (tunable; divides the columns the kernel sees) and kernel variant.
 int choose_rb(dirac_op op, dirac_prec prec, int nc, int nv, const Geom& g);

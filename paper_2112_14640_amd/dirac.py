@@ -250,8 +250,66 @@ def brillouin_links(U, antiperiodic_t=True, out=None):
     return out
 
 
+def _link_dims(U, dirs=4):
+    """(Nx,Ny,Nz,Nt), Nc of a complex128 link field (Nt,Nz,Ny,Nx,dirs,Nc,Nc) on the GPU."""
+    _require(U, "links")
+    if U.dim() != 7 or U.shape[4] != dirs or U.shape[5] != U.shape[6]:
+        raise ValueError(f"link shape {tuple(U.shape)} is not (Nt,Nz,Ny,Nx,{dirs},Nc,Nc)")
+    if U.dtype != torch.complex128:
+        raise TypeError("smearing and link gradients are FP64 (complex128)")
+    nt, nz, ny, nx = U.shape[:4]
+    d = L.Dims()
+    for i, n in enumerate((nx, ny, nz, nt)):
+        d.n[i] = n
+    d.antiperiodic_t = 1
+    return d, U.shape[-1]
+
+
+def stout_step(U, rho, out=None):
+    """One stout-smearing step (Sec. 2): V_mu(n) = exp(i Q_mu(n)) U_mu(n); FP64."""
+    d, nc = _link_dims(U)
+    out = torch.empty_like(U) if out is None else out
+    _require_like(out, "out", U)
+    L.check(L.load().dirac_stout_smear(_ptr(U), _ptr(out), float(rho), nc, C.byref(d), _stream()),
+            "dirac_stout_smear")
+    return out
+
+
+def stout_smear(U, rho=0.12, steps=3):
+    """``steps`` stout steps with parameter ``rho`` (the paper's defaults); FP64."""
+    V = U
+    for _ in range(steps):
+        V = stout_step(V, rho)
+    return V.clone() if steps == 0 else V
+
+
+def stout_backward(U, gV, rho, out=None):
+    """out += dL/dU for one stout step U -> V given gV = dL/dV (U is the step's input); FP64."""
+    d, nc = _link_dims(U)
+    _require_like(gV, "gV", U)
+    out = torch.zeros_like(U) if out is None else out
+    _require_like(out, "out", U)
+    L.check(L.load().dirac_stout_backward(_ptr(U), _ptr(gV), _ptr(out), float(rho), nc, C.byref(d), _stream()),
+            "dirac_stout_backward")
+    return out
+
+
+def brillouin_links_backward(V, gW, out=None):
+    """out += dL/dV for W = brillouin_links(V) given gW = dL/dW (40 stored directions); FP64."""
+    d, nc = _link_dims(V)
+    _link_dims(gW, 40)
+    if gW.shape[:4] != V.shape[:4] or gW.shape[-1] != nc or gW.device != V.device:
+        raise ValueError("gW does not match V")
+    out = torch.zeros_like(V) if out is None else out
+    _require_like(out, "out", V)
+    L.check(L.load().dirac_brillouin_links_backward(_ptr(V), _ptr(gW), _ptr(out), nc, C.byref(d), _stream()),
+            "dirac_brillouin_links_backward")
+    return out
+
+
 def force(op, U, psi, chi, coeff=1.0, antiperiodic_t=True, out=None):
-    """out += coeff * d Re(psi^dagger D chi) / dU (torch's complex-gradient convention); FP64."""
+    """out += coeff * d Re(psi^dagger D chi) / dU (torch's complex-gradient convention); FP64.  For the
+    Brillouin operator U is the stored-link array W and the gradient is with respect to W."""
     _require(psi, "psi")
     for t, n in ((U, "U"), (chi, "chi")):
         _require(t, n, psi.device)

@@ -144,8 +144,15 @@ def test_blas_and_misc_validation():
     assert lib.dirac_blas_workspace_bytes(12) > 0 and lib.dirac_blas_workspace_bytes(0) == 0
     assert lib.dirac_norm2(L.FP32, FAKE_A, 100, 12, FAKE_B, FAKE_G, 8, None) == L.EWORKSPACE
     assert lib.dirac_caxpy(L.FP32, FAKE_A, L.FP32, FAKE_A, FAKE_G, 100, 12, None) == L.EINVAL  # x and y alias
-    assert lib.dirac_force(L.BRILLOUIN, FAKE_G, FAKE_A, FAKE_B, 0x50000000, 1.0, 3, 2, C.byref(_dims()), None) \
+    assert lib.dirac_force(L.WILSON_LAPLACE, FAKE_G, FAKE_A, FAKE_B, 0x50000000, 1.0, 3, 2, C.byref(_dims()), None) \
         == L.EUNSUPPORTED
+    assert lib.dirac_stout_smear(FAKE_A, FAKE_A, 0.1, 3, C.byref(_dims()), None) == L.EINVAL  # U and V overlap
+    assert lib.dirac_stout_smear(FAKE_A, FAKE_B, float("nan"), 3, C.byref(_dims()), None) == L.EINVAL
+    assert lib.dirac_brillouin_links_backward(FAKE_A, None, FAKE_B, 3, C.byref(_dims()), None) == L.EINVAL
+    assert lib.dirac_clover_field(L.FP32, FAKE_A, 1.0, FAKE_A, 3, C.byref(_dims()), None) == L.EINVAL  # overlap
+    assert lib.dirac_apply_clover(L.STAGGERED, L.FP32, FAKE_G, FAKE_A, FAKE_B, 0x50000000, 0.1, 3, 2,
+                                  C.byref(_dims()), None) == L.EINVAL  # no clover term for staggered
+    assert lib.dirac_dot_noalloc(L.FP64, FAKE_A, L.FP64, FAKE_B, 4, 300, FAKE_G, None) == L.EINVAL
     assert lib.dirac_project_su(FAKE_G, FAKE_A, FAKE_B, 7, 10, None) == L.EUNSUPPORTED
     assert lib.dirac_set_launch_shape(L.BRILLOUIN, L.FP32, 4, 0) == L.EUNSUPPORTED
     assert lib.dirac_set_launch_shape(L.WILSON, L.FP32, 3, 0) == L.EINVAL
