@@ -12,11 +12,16 @@ in the 256 MB Infinity Cache.
 
 Also reported (outside the timed steps): per-kernel durations and rooflines from HIP events
 on the launch stream (against the published peaks and against the device's measured copy and
-FMA ceilings), the Brillouin link build, the same applies at the large sizes (Wilson 32^3 x 64,
-staggered and Brillouin 48^3 x 96, Haar links), the mixed-precision vs FP64 CG time-to-solution
-on D_W^dag D_W at 32^3 x 64 (Nv = 12, exp(i 0.5 H) links, m = 0.01, true FP64 relative residual
-1e-10), BiCGstab on D_B at 32^3 x 64 (mixed FP64/FP32 and plain FP64, to 1e-8), and the FP64
-NumPy oracle timed on the host on a bounded sample (12^3 x 24, same Nc, Nv).
+FMA ceilings), the Brillouin link build, the clover-improved applies (c_SW = 1) and the two
+Laplacians at the same size with the clover-field build and a stout step, the same applies at the
+large sizes (Wilson 32^3 x 64, staggered and Brillouin 48^3 x 96, Haar links), the mixed-precision
+vs FP64 CG time-to-solution on D_W^dag D_W at 32^3 x 64 (Nv = 12, exp(i 0.5 H) links, m = 0.01, true
+FP64 relative residual 1e-10; reliable updates and defect correction, FP32 and BF16 inner, each
+solution's distance from the FP64 one, a CG-Lanczos condition estimate, and the same with the clover
+term at c_SW = 1), BiCGstab on D_B at 32^3 x 64 (mixed FP64/FP32 and plain FP64, to 1e-8), and the
+FP64 NumPy oracle timed on the host (before the GPU is touched) on a bounded sample: the six applies
+at 8^4 (same Nc, Nv) on one thread and on one process per group of RHS columns, and CG iterations at
+8^4.
 Progress goes to stderr; stdout carries exactly one JSON line.
 """
 from __future__ import annotations
@@ -33,9 +38,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz without packed FP32 instructions
-FP32_VECTOR_PEAK_TFS = 78.6
-FP32_PACKED_PEAK_TFS = 157.3
+# MI355X published dense FP32 vector peak (it counts packed FP32 FMAs)
+FP32_PEAK_TFS = 157.3
+# 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz with non-packed FP32 instructions only (this
+# library is built without packed FP32): a secondary, derived denominator
+FP32_NON_PACKED_TFS = 78.6
 FP64_VECTOR_PEAK_TFS = 78.6
 
 
@@ -145,9 +152,9 @@ def run_applies(args, torch, dirac, si):
         gflops = flops / (ms * 1e-3) / 1e9
         if op == "brillouin":
             achieved = flops / (ms * 1e-3) / 1e12
-            rl = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFS, "unit": "TFLOP/s",
-                  "frac": round(achieved / FP32_VECTOR_PEAK_TFS, 4),
-                  "frac_of_packed_fp32_peak": round(achieved / FP32_PACKED_PEAK_TFS, 4)}
+            rl = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFS, "unit": "TFLOP/s",
+                  "frac": round(achieved / FP32_PEAK_TFS, 4),
+                  "frac_of_non_packed_fp32": round(achieved / FP32_NON_PACKED_TFS, 4)}
         else:
             achieved = alg_bytes / (ms * 1e-3) / 1e9
             rl = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -207,7 +214,8 @@ def run_scale(torch, dirac, si, ceil):
         r = {"lattice": list(dims), "ms": round(ms, 3), "gflops": round(flops / (ms * 1e-3) / 1e9, 1)}
         if op == "brillouin":
             tf = flops / (ms * 1e-3) / 1e12
-            r.update(bound="alu", achieved=round(tf, 2), unit="TFLOP/s", frac=round(tf / FP32_VECTOR_PEAK_TFS, 4))
+            r.update(bound="alu", achieved=round(tf, 2), unit="TFLOP/s", frac=round(tf / FP32_PEAK_TFS, 4),
+                     frac_of_non_packed_fp32=round(tf / FP32_NON_PACKED_TFS, 4))
             if ceil:
                 r["frac_of_measured"] = round(tf / ceil["fp32_fma_TFLOPs"], 4)
         else:
@@ -288,6 +296,25 @@ def run_bicgstab(torch, dirac, si):
     return out
 
 
+def lanczos_condition(alphas, betas):
+    """Extreme eigenvalues of A from the CG coefficients (CG-Lanczos): the tridiagonal T with
+    T_kk = 1/a_k + b_{k-1}/a_{k-1}, T_k,k+1 = sqrt(b_k)/a_k has A's extreme eigenvalues as its own."""
+    import numpy as np
+
+    a = np.asarray(alphas, dtype=np.float64)
+    b = np.asarray(betas, dtype=np.float64)
+    k = min(len(a), len(b) + 1)
+    if k < 2:
+        return None
+    a, b = a[:k], b[:k - 1]
+    diag = 1.0 / a
+    diag[1:] += b / a[:-1]
+    off = np.sqrt(np.maximum(b, 0.0)) / a[:-1]
+    t = np.diag(diag) + np.diag(off, 1) + np.diag(off, -1)
+    ev = np.linalg.eigvalsh(t)
+    return float(ev[0]), float(ev[-1])
+
+
 def run_cg(torch, dirac, si):
     """Mixed-precision vs FP64 CG on D_W^dag D_W at 32^3 x 64, Nv = 12, to a true residual 1e-10."""
     dev = "cuda:0"
@@ -300,56 +327,179 @@ def run_cg(torch, dirac, si):
     U32 = U.to(torch.complex64)
     b = si.complex_gaussian_t(gen, (nt, nz, ny, nx, nc, 4, nv), dev, torch.complex128)
     out = {"workload": f"CG on D_W^dag D_W, {nx}x{ny}x{nz}x{nt}, Nc={nc}, Nv={nv}, m={m}, tol=1e-10"}
-    runs = [("fp64", None, {}), ("mixed_fp32", "fp32", {}), ("mixed_bf16", "bf16", {})]
-    for name, inner, opts in runs:
+
+    def solve(name, inner, opts, clover=None, clover_lo=None, history=False, ref=None):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        x, info = dirac.cg("wilson", U, b, m, tol=1e-10, maxit=6000, inner=inner,
-                           gauge_lo=U32 if inner else None, opts=opts)
+        x, info = dirac.cg("wilson", U, b, m, tol=1e-10, maxit=6000, inner=inner, gauge_lo=U32 if inner else None,
+                           opts=opts, history=history, clover=clover, clover_lo=clover_lo)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
-        out[name] = {"seconds": round(dt, 3), "iterations": info.iterations, "fp64_recomputes": info.outer_iterations,
-                     "reason": info.reason, "max_true_relres": max(info.true_relres)}
+        r = {"seconds": round(dt, 3), "iterations": info.iterations, "fp64_recomputes": info.outer_iterations,
+             "reason": info.reason, "max_true_relres": max(info.true_relres)}
+        if ref is not None:
+            d = torch.linalg.vector_norm((x - ref).reshape(-1, nv), dim=0)
+            r["max_rel_error_vs_fp64"] = float((d / torch.linalg.vector_norm(ref.reshape(-1, nv), dim=0)).max())
         log(f"[bench] cg {name}: {dt:.2f} s, {info.iterations} it, {info.reason}, "
-            f"max relres {max(info.true_relres):.2e}")
+            f"max relres {max(info.true_relres):.2e}" + (f", error vs FP64 {r['max_rel_error_vs_fp64']:.1e}"
+                                                          if "max_rel_error_vs_fp64" in r else ""))
+        return x, info, r
+
+    x64, _, out["fp64"] = solve("fp64", None, {})
+    runs = [("mixed_fp32", "fp32", {}), ("mixed_bf16", "bf16", {}),
+            ("mixed_fp32_defect_correction", "fp32", {"mixed_scheme": 1}),
+            ("mixed_bf16_defect_correction", "bf16", {"mixed_scheme": 1})]
+    for name, inner, opts in runs:
+        x, _, out[name] = solve(name, inner, opts, ref=x64)
         del x
-        torch.cuda.empty_cache()
     base = out["fp64"]["seconds"]
-    for name in ("mixed_fp32", "mixed_bf16"):
+    for name, _, _ in runs:
         if out[name]["reason"] == "converged":
             out[name]["speedup_vs_fp64"] = round(base / out[name]["seconds"], 3)
+    # condition number of D^dag D from the FP64 CG coefficients (an untimed repeat that keeps them)
+    x, info, _ = solve("fp64 (history)", None, {}, history=True)
+    del x
+    conds = []
+    for i in range(nv):
+        ext = lanczos_condition([a[i] for a in info.alphas], [bb[i] for bb in info.betas])
+        if ext:
+            conds.append(ext)
+    if conds:
+        out["lanczos"] = {"lambda_min": min(c[0] for c in conds), "lambda_max": max(c[1] for c in conds),
+                          "cond_max_over_rhs": max(c[1] / c[0] for c in conds),
+                          "how": "extreme Ritz values of the CG-Lanczos tridiagonal per RHS (FP64 CG)"}
+        log(f"[bench] cg condition estimate {out['lanczos']['cond_max_over_rhs']:.3e}")
+    # the paper's solver setting: clover term with c_SW = 1 (Sec. 9)
+    C64 = dirac.clover_field(U, 1.0)
+    C32 = dirac.clover_field(U32, 1.0)
+    xc, _, rc64 = solve("clover fp64", None, {}, clover=C64)
+    _, _, rcbf = solve("clover mixed_bf16", "bf16", {}, clover=C64, clover_lo=C32, ref=xc)
+    if rcbf["reason"] == "converged":
+        rcbf["speedup_vs_fp64"] = round(rc64["seconds"] / rcbf["seconds"], 3)
+    out["clover_csw1"] = {"fp64": rc64, "mixed_bf16": rcbf}
+    del xc, x64, C64, C32
+    torch.cuda.empty_cache()
     return out
 
 
-def run_cpu_baseline(si):
-    """The FP64 NumPy oracle on the host: the same six applies on a 12^3 x 24 sample lattice."""
-    import numpy as np
+def run_extras(torch, dirac, si):
+    """The clover-improved applies (c_SW = 1), the Laplacians, the clover field and a stout step at
+    16^3 x 32, Nc = 3, Nv = 12, FP32 (stout: FP64), each timed over repeated launches by HIP events."""
+    dev = "cuda:0"
+    cfg = si.config("apply_16x32")
+    dims, nc, nv, m = cfg["dims"], cfg["nc"], cfg["nv"], cfg["mass"]
+    nx, ny, nz, nt = dims
+    vol = nx * ny * nz * nt
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1500)
+    U = si.near_identity_su_n_t(gen, (nt, nz, ny, nx, 4), nc, cfg["spread"], dev, torch.complex64)
+    W = dirac.brillouin_links(U)
+    psi = si.complex_gaussian_t(gen, (nt, nz, ny, nx, nc, 4, nv), dev, torch.complex64)
+    v = torch.empty_like(psi)
+    out = {}
+    C = dirac.clover_field(U, 1.0)
+    out["clover_field_ms"] = round(time_apply(torch, lambda: dirac.clover_field(U, 1.0, out=C), 5), 3)
+    U64 = U.to(torch.complex128)
+    out["stout_step_fp64_ms"] = round(time_apply(torch, lambda: dirac.stout_step(U64, 0.12), 5), 3)
+    del U64
+    clover_flops = 64 * nc * nc  # App. E.6 with the sigma structure used
+    for name, op, gauge, kw, fl in (
+            ("wilson_clover", "wilson", U, {"clover": C}, dirac.flops_per_site("wilson", nc) + clover_flops),
+            ("brillouin_clover", "brillouin", W, {"clover": C},
+             dirac.flops_per_site("brillouin", nc) + clover_flops),
+            ("wilson_laplace", "wilson_laplace", U, {}, dirac.flops_per_site("wilson_laplace", nc)),
+            ("brillouin_laplace", "brillouin_laplace", W, {}, dirac.flops_per_site("brillouin_laplace", nc))):
+        ms = time_apply(torch, lambda: dirac.apply(op, gauge, psi, m, out=v, **kw), 20)
+        dirs = 40 if "brillouin" in op else 4
+        alg = (2 * 2 * nc * 4 * nv * 4 + dirs * 2 * nc * nc * 4 + (8 * nc * nc * 4 if "clover" in name else 0)) * vol
+        out[name] = {"ms": round(ms, 4), "gflops": round(fl * vol * nv / (ms * 1e-3) / 1e9, 1),
+                     "hbm_GBps": round(alg / (ms * 1e-3) / 1e9, 1), "alg_bytes": alg}
+        log(f"[bench] {name}: {ms:.3f} ms, {out[name]['gflops']} GFLOP/s")
+    del U, W, psi, v, C
+    torch.cuda.empty_cache()
+    return out
 
-    from oracle.brillouin import brillouin_apply, brillouin_apply_dagger, brillouin_links
+
+def _cpu_worker(args):
+    """Child process: the six oracle applies on a slice of the RHS columns, one BLAS thread."""
+    lo, hi = args
+    from threadpoolctl import threadpool_limits
+
+    g = _CPU_STATE
+    with threadpool_limits(1):
+        _six_applies(g, slice(lo, hi))
+    return hi - lo
+
+
+_CPU_STATE = {}
+
+
+def _six_applies(g, cols):
+    from oracle.brillouin import brillouin_apply, brillouin_apply_dagger
     from oracle.staggered import staggered_apply, staggered_apply_dagger
     from oracle.wilson import wilson_apply, wilson_apply_dagger
 
-    dims, nc, nv, m = (12, 12, 12, 24), 3, 12, 0.05
-    vol = 12 * 12 * 12 * 24
+    psi, phi = g["psi"][..., cols], g["phi"][..., cols]
+    for fn, gauge, v in ((wilson_apply, g["U"], psi), (wilson_apply_dagger, g["U"], psi),
+                         (brillouin_apply, g["W"], psi), (brillouin_apply_dagger, g["W"], psi),
+                         (staggered_apply, g["U"], phi), (staggered_apply_dagger, g["U"], phi)):
+        fn(gauge, v, g["m"])
+
+
+def run_cpu_baseline(si):
+    """The FP64 NumPy oracle on the host (run before the GPU is initialised): the six applies on an
+    8^4 sample lattice (Nc = 3, Nv = 12) once on one thread and three times on one process per group
+    of RHS columns (best of three), and CG iterations on D_W^dag D_W at 8^4."""
+    import multiprocessing as mp
+
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle.brillouin import brillouin_links
+    from oracle.solvers import cg as oracle_cg
+    from oracle.wilson import wilson_apply, wilson_apply_dagger
+
+    dims, nc, nv, m = (8, 8, 8, 8), 3, 12, 0.05
+    vol = 8 * 8 * 8 * 8
     rng = np.random.default_rng(0)
     U = si.gauge_field(rng, dims, nc, "near", 0.3)
-    psi = si.wilson_vector(rng, dims, nc, nv)
-    phi = si.staggered_vector(rng, dims, nc, nv)
-    W = brillouin_links(U)
-    calls = [(wilson_apply, U, psi, 128 * 9 + 72 * 3), (wilson_apply_dagger, U, psi, 128 * 9 + 72 * 3),
-             (brillouin_apply, W, psi, 2560 * 9 + 2376 * 3), (brillouin_apply_dagger, W, psi, 2560 * 9 + 2376 * 3),
-             (staggered_apply, U, phi, 64 * 9 + 6), (staggered_apply_dagger, U, phi, 64 * 9 + 6)]
-    total_t, total_f = 0.0, 0.0
-    for fn, g, v, f in calls:
+    _CPU_STATE.update(U=U, W=brillouin_links(U), psi=si.wilson_vector(rng, dims, nc, nv),
+                      phi=si.staggered_vector(rng, dims, nc, nv), m=m)
+    flops = 2 * (128 * 9 + 72 * 3 + 2560 * 9 + 2376 * 3 + 64 * 9 + 6) * vol * nv
+    with threadpool_limits(1):
         t = time.perf_counter()
-        fn(g, v, m)
-        total_t += time.perf_counter() - t
-        total_f += f * vol * nv
-    log(f"[bench] cpu oracle: {total_t:.2f} s for the six applies on 12^3x24")
-    return {"value": round(total_f / total_t / 1e9, 4), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": "the six applies (W, W^dag, B, B^dag, S, S^dag) once each on a 12^3x24 lattice, Nc=3, Nv=12, "
-                      "FP64 NumPy, single thread", "seconds": round(total_t, 2),
-            "host_cores_available": len(os.sched_getaffinity(0))}
+        _six_applies(_CPU_STATE, slice(0, nv))
+        one = time.perf_counter() - t
+    cores = len(os.sched_getaffinity(0))
+    procs = max(1, min(nv, cores, 16))
+    chunks = [(i * nv // procs, (i + 1) * nv // procs) for i in range(procs)]
+    best = None
+    with mp.get_context("fork").Pool(procs) as pool:
+        for _ in range(3):
+            t = time.perf_counter()
+            pool.map(_cpu_worker, chunks)
+            dt = time.perf_counter() - t
+            best = dt if best is None else min(best, dt)
+    log(f"[bench] cpu oracle: six applies at 8^4 {one:.2f} s on 1 thread, {best:.2f} s on {procs} processes")
+    # CG on D_W^dag D_W at 8^4: time per iteration over a fixed 4 iterations, one thread
+    b = si.wilson_vector(np.random.default_rng(1), dims, nc, nv)
+
+    def a_op(x):
+        return wilson_apply_dagger(U, wilson_apply(U, x, m), m)
+
+    with threadpool_limits(1):
+        t = time.perf_counter()
+        res = oracle_cg(a_op, b, tol=1e-30, maxit=4)
+        cg_dt = time.perf_counter() - t
+    its = max(1, len(res.alphas))
+    _CPU_STATE.clear()
+    return {"value": round(flops / best / 1e9, 4), "unit": "GFLOP/s", "cores": procs, "kind": "oracle",
+            "sample": "the six applies (W, W^dag, B, B^dag, S, S^dag) on an 8^4 lattice, Nc=3, Nv=12, FP64 NumPy, "
+                      f"{procs} processes with one thread each over groups of RHS columns, best of 3",
+            "seconds": round(best, 3), "one_thread": {"value": round(flops / one / 1e9, 4), "seconds": round(one, 3)},
+            "cg_per_iteration_s": round(cg_dt / its, 4),
+            "cg_sample": f"CG on D_W^dag D_W at 8^4, Nv=12, {its} iterations, one thread",
+            "host_cores_available": cores}
 
 
 def main():
@@ -370,9 +520,14 @@ def main():
               "domain decomposition is designed but not implemented)", file=sys.stderr)
         sys.exit(2)
 
+    import synthetic_inputs as si
+
+    # the oracle's host baseline runs first, before anything touches the GPU (its worker processes are
+    # forked from this one)
+    cpu = None if args.no_cpu else run_cpu_baseline(si)
+
     import torch
 
-    import synthetic_inputs as si
     from paper_2112_14640_amd import dirac
 
     torch.cuda.set_device(0)
@@ -390,10 +545,10 @@ def main():
         for name, r in res["rooflines"].items():
             r["frac_of_measured"] = round(r["achieved"] / (ceil["fp32_fma_TFLOPs"] if r["bound"] == "alu"
                                                            else ceil["copy_GBps"]), 4)
+    extras = None if args.no_scale else run_extras(torch, dirac, si)
     scale = None if args.no_scale else run_scale(torch, dirac, si, ceil)
     cg = None if args.no_cg else run_cg(torch, dirac, si)
     bicg = None if (args.no_cg or args.no_scale) else run_bicgstab(torch, dirac, si)
-    cpu = None if args.no_cpu else run_cpu_baseline(si)
     nx, ny, nz, nt = res["dims"]
     rl = dict(res["rooflines"][res["dominant"]])
     line = {
@@ -412,11 +567,12 @@ def main():
         "config": {"workload": f"Wilson, Brillouin and staggered applies and adjoints, {nx}x{ny}x{nz}x{nt}, "
                                f"Nc={res['nc']}, Nv={res['nv']}, FP32, exp(i 0.3 H) links, m=0.05",
                    "lattice": [nx, ny, nz, nt], "nc": res["nc"], "nv": res["nv"], "input_sets_rotated": args.sets},
-        "roofline": {k: rl[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic", "frac_of_measured")
-                     if k in rl},
+        "roofline": {k: rl[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic", "frac_of_measured",
+                                        "frac_of_non_packed_fp32") if k in rl},
         "roofline_kernel": res["dominant"],
         "kernels": res["rooflines"],
         "brillouin_link_build_ms": res["link_build_ms"],
+        "clover_laplace_stout": extras,
         "ceilings": ceil,
         "scale": scale,
         "cg": cg,
