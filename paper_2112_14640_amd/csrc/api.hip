@@ -135,10 +135,15 @@ int choose_variant(dirac_op op, dirac_prec prec) {
 }
 
 int launch_stencil(dirac_op op, dirac_prec prec, int nc, int nv, const Geom& g, double mass, const void* gauge,
-                   const void* clover, const void* in, void* out, bool dag, hipStream_t st) {
+                   const void* clover, const void* in, void* out, bool dag, hipStream_t st, const Epilogue& epi) {
     StencilArgs a{prec, nc, nv, choose_rb(op, prec, nc, nv, g), choose_variant(op, prec), dag, mass, g, gauge, in, out};
     a.clover = op_takes_clover(op) ? clover : nullptr;
     a.laplace = op_is_laplace(op);
+    if (epi.mode != 0) {
+        // the solver epilogues exist on the Wilson and staggered row kernels only
+        if (op != DIRAC_WILSON && op != DIRAC_STAGGERED) return kNoEpilogue;
+        a.epi = epi;
+    }
     if (a.laplace) a.dagger = false;  // hermitian
     switch (op) {
         case DIRAC_WILSON: return launch_wilson(a, st);

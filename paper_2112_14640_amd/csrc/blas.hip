@@ -7,6 +7,8 @@
 // block handles rows blockIdx + k * gridDim in a fixed order and reduces per RHS through
 // LDS in a fixed order, then one block per output value adds the block partials with a
 // fixed tree.  Repeated runs give bitwise identical results.
+#include <algorithm>
+#include <initializer_list>
 #include <mutex>
 
 #include "common.h"
@@ -48,6 +50,99 @@ __device__ __forceinline__ cx<double> stored_value(cx<double> v) {
     return io<double, S>::ld(&tmp);
 }
 
+// Packs: VW consecutive complex elements of one row (consecutive right-hand sides) moved with a single
+// 4-, 8- or 16-byte access, so that FP32 and BF16 vectors stream with the same 16-byte lane accesses
+// as FP64 ones.  VW = 16 bytes / the widest element of a kernel's vectors (1 when that does not divide
+// nv or a pointer is not aligned to the pack).
+using pk_u32x2 = unsigned int __attribute__((ext_vector_type(2)));
+using pk_u32x4 = unsigned int __attribute__((ext_vector_type(4)));
+template <int BYTES>
+struct RawT;
+template <>
+struct RawT<4> {
+    using T = unsigned int;
+};
+template <>
+struct RawT<8> {
+    using T = pk_u32x2;
+};
+template <>
+struct RawT<16> {
+    using T = pk_u32x4;
+};
+template <typename S, int VW>
+struct Pack {
+    S e[VW];
+};
+
+template <int VW, typename S>
+__device__ __forceinline__ void ldp(const S* p, cx<double> (&v)[VW]) {
+    using T = typename RawT<sizeof(S) * VW>::T;
+    const Pack<S, VW> pk = __builtin_bit_cast(Pack<S, VW>, *reinterpret_cast<const T*>(p));
+#pragma unroll
+    for (int i = 0; i < VW; ++i) v[i] = ldd(&pk.e[i]);
+}
+
+template <int VW, typename S>
+__device__ __forceinline__ void stp(S* p, const cx<double> (&v)[VW]) {
+    using T = typename RawT<sizeof(S) * VW>::T;
+    Pack<S, VW> pk;
+#pragma unroll
+    for (int i = 0; i < VW; ++i) std_(&pk.e[i], v[i]);
+    *reinterpret_cast<T*>(p) = __builtin_bit_cast(T, pk);
+}
+
+template <typename... S>
+constexpr int pack_width() {
+    constexpr size_t m = std::max({sizeof(S)...});
+    return static_cast<int>(16 / m);
+}
+
+inline bool pack_ok(int vw, int nv, std::initializer_list<const void*> ptrs) {
+    if (vw <= 1) return true;
+    if (nv % vw != 0) return false;
+    for (const void* p : ptrs)
+        if (reinterpret_cast<uintptr_t>(p) % 16 != 0) return false;
+    return true;
+}
+
+// Packed row lanes: rows of nvp = nv / VW packs; thread (roff, pk) handles pack pk of row
+// blockIdx * rpb + roff + k * gridDim * rpb.
+struct PackLane {
+    int nvp, rpb, roff, pk;
+};
+__device__ __forceinline__ PackLane pack_lane(int nvp) {
+    PackLane r;
+    r.nvp = nvp;
+    r.rpb = kReduceThreads / nvp;
+    r.roff = threadIdx.x / nvp;
+    r.pk = threadIdx.x - r.roff * nvp;
+    return r;
+}
+
+// Per-block per-RHS partial sums of W values for each of the VW elements of a thread's pack, written as
+// partial[(block * W + w) * nv + rhs] (the layout finalize() reads); fixed summation order.
+template <int W, int VW>
+__device__ __forceinline__ void block_partials_packed(const double (&v)[W][VW], const PackLane& pl, double* partial) {
+    __shared__ double sh[W * VW][kReduceThreads];
+    const bool act = pl.roff < pl.rpb;
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+#pragma unroll
+        for (int i = 0; i < VW; ++i) sh[w * VW + i][threadIdx.x] = act ? v[w][i] : 0.0;
+    __syncthreads();
+    const int nv = pl.nvp * VW;
+    if (static_cast<int>(threadIdx.x) < nv) {
+        const int pk = threadIdx.x / VW, i = threadIdx.x - pk * VW;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            double s = 0.0;
+            for (int j = 0; j < pl.rpb; ++j) s += sh[w * VW + i][j * pl.nvp + pk];
+            partial[(static_cast<int64_t>(blockIdx.x) * W + w) * nv + threadIdx.x] = s;
+        }
+    }
+}
+
 // Row/RHS position of this thread inside the reduction block layout.
 struct RowLane {
     int rpb;   // rows per block step
@@ -81,13 +176,13 @@ __device__ __forceinline__ void block_partials(const double (&v)[W], int nv, con
 
 // out[rhs*W + w] = sum over blocks of partial[(b*W + w)*nv + rhs]; one block per (w, rhs).
 // For W = 2 the result is interleaved (re, im) per RHS, i.e. usable as complex coefficients.
-__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partial, int nblk, int width_w, int nv,
+__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partial, int64_t nblk, int width_w, int nv,
                                                   double* __restrict__ out) {
     __shared__ double sh[256];
     const int j = blockIdx.x;  // j = w*nv + rhs
     const int w = j / nv, rhs = j - w * nv;
     double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += 256) s += partial[(static_cast<int64_t>(b) * width_w + w) * nv + rhs];
+    for (int64_t b = threadIdx.x; b < nblk; b += 256) s += partial[(b * width_w + w) * nv + rhs];
     sh[threadIdx.x] = s;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
@@ -98,41 +193,48 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
 }
 
 void finalize(const double* partial, int width_w, int nv, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_finalize, dim3(width_w * nv), dim3(256), 0, st, partial, kReduceBlocks, width_w, nv, out);
+    hipLaunchKernelGGL(k_finalize, dim3(width_w * nv), dim3(256), 0, st, partial, static_cast<int64_t>(kReduceBlocks),
+                       width_w, nv, out);
 }
 
-template <typename SX>
+template <int VW, typename SX>
 __global__ __launch_bounds__(kReduceThreads) void k_norm2(const SX* __restrict__ x, int64_t nrows, int nv,
                                                            double* __restrict__ partial) {
-    const RowLane rl = row_lane(nv);
-    double acc[1] = {0.0};
-    if (rl.roff < rl.rpb) {
-        const int64_t step = static_cast<int64_t>(gridDim.x) * rl.rpb;
-#pragma unroll 4
-        for (int64_t row = static_cast<int64_t>(blockIdx.x) * rl.rpb + rl.roff; row < nrows; row += step) {
-            cx<double> v = ldd(x + row * nv + rl.rhs);
-            acc[0] += v.re * v.re + v.im * v.im;
+    const PackLane pl = pack_lane(nv / VW);
+    double acc[1][VW] = {};
+    if (pl.roff < pl.rpb) {
+        const int64_t step = static_cast<int64_t>(gridDim.x) * pl.rpb;
+#pragma unroll 2
+        for (int64_t row = static_cast<int64_t>(blockIdx.x) * pl.rpb + pl.roff; row < nrows; row += step) {
+            cx<double> v[VW];
+            ldp<VW>(x + row * nv + pl.pk * VW, v);
+#pragma unroll
+            for (int i = 0; i < VW; ++i) acc[0][i] += v[i].re * v[i].re + v[i].im * v[i].im;
         }
     }
-    block_partials<1>(acc, nv, rl, partial);
+    block_partials_packed<1, VW>(acc, pl, partial);
 }
 
-template <typename SX, typename SY>
+template <int VW, typename SX, typename SY>
 __global__ __launch_bounds__(kReduceThreads) void k_dot(const SX* __restrict__ x, const SY* __restrict__ y,
                                                          int64_t nrows, int nv, double* __restrict__ partial) {
-    const RowLane rl = row_lane(nv);
-    double acc[2] = {0.0, 0.0};
-    if (rl.roff < rl.rpb) {
-        const int64_t step = static_cast<int64_t>(gridDim.x) * rl.rpb;
-#pragma unroll 4
-        for (int64_t row = static_cast<int64_t>(blockIdx.x) * rl.rpb + rl.roff; row < nrows; row += step) {
-            cx<double> a = ldd(x + row * nv + rl.rhs);
-            cx<double> b = ldd(y + row * nv + rl.rhs);
-            acc[0] += a.re * b.re + a.im * b.im;
-            acc[1] += a.re * b.im - a.im * b.re;
+    const PackLane pl = pack_lane(nv / VW);
+    double acc[2][VW] = {};
+    if (pl.roff < pl.rpb) {
+        const int64_t step = static_cast<int64_t>(gridDim.x) * pl.rpb;
+#pragma unroll 2
+        for (int64_t row = static_cast<int64_t>(blockIdx.x) * pl.rpb + pl.roff; row < nrows; row += step) {
+            cx<double> a[VW], b[VW];
+            ldp<VW>(x + row * nv + pl.pk * VW, a);
+            ldp<VW>(y + row * nv + pl.pk * VW, b);
+#pragma unroll
+            for (int i = 0; i < VW; ++i) {
+                acc[0][i] += a[i].re * b[i].re + a[i].im * b[i].im;
+                acc[1][i] += a[i].re * b[i].im - a[i].im * b[i].re;
+            }
         }
     }
-    block_partials<2>(acc, nv, rl, partial);
+    block_partials_packed<2, VW>(acc, pl, partial);
 }
 
 // Elementwise kernels: grid-stride over complex elements, rhs = element % nv.
@@ -228,78 +330,108 @@ __global__ __launch_bounds__(256) void k_epsilon(const S* __restrict__ x, S* __r
 }
 
 // r -= alpha q ; partial ||r||^2
-template <typename SR, typename SQ>
+template <int VW, typename SR, typename SQ>
 __global__ __launch_bounds__(kReduceThreads) void k_r_update(SR* __restrict__ r, const SQ* __restrict__ q,
                                                               const double2* __restrict__ alpha, int64_t nrows,
                                                               int nv, double* __restrict__ partial) {
-    const RowLane rl = row_lane(nv);
-    double acc[1] = {0.0};
-    if (rl.roff < rl.rpb) {
-        const double2 al = alpha[rl.rhs];
-        const cx<double> ma{-al.x, -al.y};
-        const int64_t step = static_cast<int64_t>(gridDim.x) * rl.rpb;
-#pragma unroll 4
-        for (int64_t row = static_cast<int64_t>(blockIdx.x) * rl.rpb + rl.roff; row < nrows; row += step) {
-            const int64_t i = row * nv + rl.rhs;
-            cx<double> rv = ldd(r + i);
-            cfma(rv, ma, ldd(q + i));
-            std_(r + i, rv);
-            const cx<double> st = stored_value<SR>(rv);  // norm of the value as stored
-            acc[0] += st.re * st.re + st.im * st.im;
+    const PackLane pl = pack_lane(nv / VW);
+    double acc[1][VW] = {};
+    if (pl.roff < pl.rpb) {
+        cx<double> ma[VW];
+#pragma unroll
+        for (int i = 0; i < VW; ++i) {
+            const double2 al = alpha[pl.pk * VW + i];
+            ma[i] = {-al.x, -al.y};
+        }
+        const int64_t step = static_cast<int64_t>(gridDim.x) * pl.rpb;
+#pragma unroll 2
+        for (int64_t row = static_cast<int64_t>(blockIdx.x) * pl.rpb + pl.roff; row < nrows; row += step) {
+            const int64_t e = row * nv + pl.pk * VW;
+            cx<double> rv[VW], qv[VW];
+            ldp<VW>(r + e, rv);
+            ldp<VW>(q + e, qv);
+#pragma unroll
+            for (int i = 0; i < VW; ++i) cfma(rv[i], ma[i], qv[i]);
+            stp<VW>(r + e, rv);
+#pragma unroll
+            for (int i = 0; i < VW; ++i) {
+                const cx<double> st = stored_value<SR>(rv[i]);  // norm of the value as stored
+                acc[0][i] += st.re * st.re + st.im * st.im;
+            }
         }
     }
-    block_partials<1>(acc, nv, rl, partial);
+    block_partials_packed<1, VW>(acc, pl, partial);
 }
 
-// x += alpha p ; p = r + beta p
-template <typename SX, typename SP, typename SR>
+// x += alpha p ; p = r + beta p (packs of VW elements, grid-stride)
+template <int VW, typename SX, typename SP, typename SR>
 __global__ __launch_bounds__(256) void k_xp_update(SX* __restrict__ x, SP* __restrict__ p, const SR* __restrict__ r,
                                                     const double2* __restrict__ alpha,
                                                     const double2* __restrict__ beta, int64_t n, int nv) {
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+    const int64_t npk = n / VW;
+    const int nvp = nv / VW;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < npk;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const int k = static_cast<int>(i % nv);
-        const double2 al = alpha[k], be = beta[k];
-        const cx<double> pv = ldd(p + i);
-        cx<double> xv = ldd(x + i);
-        cfma(xv, cx<double>{al.x, al.y}, pv);
-        std_(x + i, xv);
-        cx<double> np = ldd(r + i);
-        cfma(np, cx<double>{be.x, be.y}, pv);
-        std_(p + i, np);
+        const int k0 = static_cast<int>(i % nvp) * VW;
+        const int64_t e = i * VW;
+        cx<double> pv[VW], xv[VW], rv[VW];
+        ldp<VW>(p + e, pv);
+        ldp<VW>(x + e, xv);
+        ldp<VW>(r + e, rv);
+#pragma unroll
+        for (int j = 0; j < VW; ++j) {
+            const double2 al = alpha[k0 + j], be = beta[k0 + j];
+            cfma(xv[j], cx<double>{al.x, al.y}, pv[j]);
+            cfma(rv[j], cx<double>{be.x, be.y}, pv[j]);
+        }
+        stp<VW>(x + e, xv);
+        stp<VW>(p + e, rv);
     }
 }
 
 // x += alpha p ; p = r + beta p ; partial <r, p> of the new p as stored (the line-search numerator
 // of the next step; reads and writes nothing beyond k_xp_update)
-template <typename SX, typename SP, typename SR>
+template <int VW, typename SX, typename SP, typename SR>
 __global__ __launch_bounds__(kReduceThreads) void k_xp_update_dot(SX* __restrict__ x, SP* __restrict__ p,
                                                                    const SR* __restrict__ r,
                                                                    const double2* __restrict__ alpha,
                                                                    const double2* __restrict__ beta, int64_t nrows,
                                                                    int nv, double* __restrict__ partial) {
-    const RowLane rl = row_lane(nv);
-    double acc[2] = {0.0, 0.0};
-    if (rl.roff < rl.rpb) {
-        const double2 al = alpha[rl.rhs], be = beta[rl.rhs];
-        const int64_t step = static_cast<int64_t>(gridDim.x) * rl.rpb;
-#pragma unroll 4
-        for (int64_t row = static_cast<int64_t>(blockIdx.x) * rl.rpb + rl.roff; row < nrows; row += step) {
-            const int64_t i = row * nv + rl.rhs;
-            const cx<double> pv = ldd(p + i);
-            cx<double> xv = ldd(x + i);
-            cfma(xv, cx<double>{al.x, al.y}, pv);
-            std_(x + i, xv);
-            const cx<double> rv = ldd(r + i);
-            cx<double> np = rv;
-            cfma(np, cx<double>{be.x, be.y}, pv);
-            std_(p + i, np);
-            const cx<double> ps = stored_value<SP>(np);  // <r, p> of p as stored
-            acc[0] += rv.re * ps.re + rv.im * ps.im;
-            acc[1] += rv.re * ps.im - rv.im * ps.re;
+    const PackLane pl = pack_lane(nv / VW);
+    double acc[2][VW] = {};
+    if (pl.roff < pl.rpb) {
+        cx<double> al[VW], be[VW];
+#pragma unroll
+        for (int i = 0; i < VW; ++i) {
+            const double2 a = alpha[pl.pk * VW + i], b = beta[pl.pk * VW + i];
+            al[i] = {a.x, a.y};
+            be[i] = {b.x, b.y};
+        }
+        const int64_t step = static_cast<int64_t>(gridDim.x) * pl.rpb;
+#pragma unroll 2
+        for (int64_t row = static_cast<int64_t>(blockIdx.x) * pl.rpb + pl.roff; row < nrows; row += step) {
+            const int64_t e = row * nv + pl.pk * VW;
+            cx<double> pv[VW], xv[VW], rv[VW], np[VW];
+            ldp<VW>(p + e, pv);
+            ldp<VW>(x + e, xv);
+            ldp<VW>(r + e, rv);
+#pragma unroll
+            for (int i = 0; i < VW; ++i) {
+                cfma(xv[i], al[i], pv[i]);
+                np[i] = rv[i];
+                cfma(np[i], be[i], pv[i]);
+            }
+            stp<VW>(x + e, xv);
+            stp<VW>(p + e, np);
+#pragma unroll
+            for (int i = 0; i < VW; ++i) {
+                const cx<double> ps = stored_value<SP>(np[i]);  // <r, p> of p as stored
+                acc[0][i] += rv[i].re * ps.re + rv[i].im * ps.im;
+                acc[1][i] += rv[i].re * ps.im - rv[i].im * ps.re;
+            }
         }
     }
-    block_partials<2>(acc, nv, rl, partial);
+    block_partials_packed<2, VW>(acc, pl, partial);
 }
 
 // BiCGstab: x += alpha p + omega s ; r = s - omega t ; partial ||r||^2
@@ -365,11 +497,20 @@ __global__ __launch_bounds__(256) void k_bicg_s(S* __restrict__ s, const S* __re
 
 }  // namespace
 
+void finalize_blocks(const double* partial, int64_t nblk, int nv, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize, dim3(nv), dim3(256), 0, st, partial, nblk, 1, nv, out);
+}
+
 int blas_norm2(dirac_prec p, const void* x, int64_t nrows, int nv, double* partial, double* out, hipStream_t st) {
     return with_prec(p, [&](auto tx) {
         using SX = typename decltype(tx)::type;
-        hipLaunchKernelGGL((k_norm2<SX>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, st,
-                           static_cast<const SX*>(x), nrows, nv, partial);
+        constexpr int VW = pack_width<SX>();
+        if (pack_ok(VW, nv, {x}))
+            hipLaunchKernelGGL((k_norm2<VW, SX>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, st,
+                               static_cast<const SX*>(x), nrows, nv, partial);
+        else
+            hipLaunchKernelGGL((k_norm2<1, SX>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, st,
+                               static_cast<const SX*>(x), nrows, nv, partial);
         finalize(partial, 1, nv, out, st);
         return DIRAC_OK;
     });
@@ -381,8 +522,13 @@ int blas_dot(dirac_prec px, const void* x, dirac_prec py, const void* y, int64_t
         return with_prec(py, [&](auto ty) {
             using SX = typename decltype(tx)::type;
             using SY = typename decltype(ty)::type;
-            hipLaunchKernelGGL((k_dot<SX, SY>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, st,
-                               static_cast<const SX*>(x), static_cast<const SY*>(y), nrows, nv, partial);
+            constexpr int VW = pack_width<SX, SY>();
+            if (pack_ok(VW, nv, {x, y}))
+                hipLaunchKernelGGL((k_dot<VW, SX, SY>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, st,
+                                   static_cast<const SX*>(x), static_cast<const SY*>(y), nrows, nv, partial);
+            else
+                hipLaunchKernelGGL((k_dot<1, SX, SY>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, st,
+                                   static_cast<const SX*>(x), static_cast<const SY*>(y), nrows, nv, partial);
             finalize(partial, 2, nv, out, st);
             return DIRAC_OK;
         });
@@ -499,9 +645,15 @@ int fused_r_update(dirac_prec pr, void* r, dirac_prec pq, const void* q, const d
         return with_prec(pq, [&](auto tq) {
             using SR = typename decltype(tr)::type;
             using SQ = typename decltype(tq)::type;
-            hipLaunchKernelGGL((k_r_update<SR, SQ>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, st,
-                               static_cast<SR*>(r), static_cast<const SQ*>(q),
-                               reinterpret_cast<const double2*>(alpha), nrows, nv, partial);
+            constexpr int VW = pack_width<SR, SQ>();
+            if (pack_ok(VW, nv, {r, q}))
+                hipLaunchKernelGGL((k_r_update<VW, SR, SQ>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, st,
+                                   static_cast<SR*>(r), static_cast<const SQ*>(q),
+                                   reinterpret_cast<const double2*>(alpha), nrows, nv, partial);
+            else
+                hipLaunchKernelGGL((k_r_update<1, SR, SQ>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, st,
+                                   static_cast<SR*>(r), static_cast<const SQ*>(q),
+                                   reinterpret_cast<const double2*>(alpha), nrows, nv, partial);
             finalize(partial, 1, nv, rr, st);
             return DIRAC_OK;
         });
@@ -517,10 +669,17 @@ int fused_xp_update(dirac_prec px, void* x, dirac_prec pp, void* p, dirac_prec p
                 using SX = typename decltype(tx)::type;
                 using SP = typename decltype(tp)::type;
                 using SR = typename decltype(trr)::type;
-                hipLaunchKernelGGL((k_xp_update<SX, SP, SR>), ew_grid(n), dim3(256), 0, st, static_cast<SX*>(x),
-                                   static_cast<SP*>(p), static_cast<const SR*>(r),
-                                   reinterpret_cast<const double2*>(alpha), reinterpret_cast<const double2*>(beta), n,
-                                   nv);
+                constexpr int VW = pack_width<SX, SP, SR>();
+                if (pack_ok(VW, nv, {x, p, r}))
+                    hipLaunchKernelGGL((k_xp_update<VW, SX, SP, SR>), ew_grid(n / VW), dim3(256), 0, st,
+                                       static_cast<SX*>(x), static_cast<SP*>(p), static_cast<const SR*>(r),
+                                       reinterpret_cast<const double2*>(alpha), reinterpret_cast<const double2*>(beta),
+                                       n, nv);
+                else
+                    hipLaunchKernelGGL((k_xp_update<1, SX, SP, SR>), ew_grid(n), dim3(256), 0, st,
+                                       static_cast<SX*>(x), static_cast<SP*>(p), static_cast<const SR*>(r),
+                                       reinterpret_cast<const double2*>(alpha), reinterpret_cast<const double2*>(beta),
+                                       n, nv);
                 return DIRAC_OK;
             });
         });
@@ -536,10 +695,17 @@ int fused_xp_update_dot(dirac_prec px, void* x, dirac_prec pp, void* p, dirac_pr
                 using SX = typename decltype(tx)::type;
                 using SP = typename decltype(tp)::type;
                 using SR = typename decltype(trr)::type;
-                hipLaunchKernelGGL((k_xp_update_dot<SX, SP, SR>), dim3(kReduceBlocks), dim3(kReduceThreads), 0, st,
-                                   static_cast<SX*>(x), static_cast<SP*>(p), static_cast<const SR*>(r),
-                                   reinterpret_cast<const double2*>(alpha), reinterpret_cast<const double2*>(beta),
-                                   nrows, nv, partial);
+                constexpr int VW = pack_width<SX, SP, SR>();
+                if (pack_ok(VW, nv, {x, p, r}))
+                    hipLaunchKernelGGL((k_xp_update_dot<VW, SX, SP, SR>), dim3(kReduceBlocks), dim3(kReduceThreads), 0,
+                                       st, static_cast<SX*>(x), static_cast<SP*>(p), static_cast<const SR*>(r),
+                                       reinterpret_cast<const double2*>(alpha), reinterpret_cast<const double2*>(beta),
+                                       nrows, nv, partial);
+                else
+                    hipLaunchKernelGGL((k_xp_update_dot<1, SX, SP, SR>), dim3(kReduceBlocks), dim3(kReduceThreads), 0,
+                                       st, static_cast<SX*>(x), static_cast<SP*>(p), static_cast<const SR*>(r),
+                                       reinterpret_cast<const double2*>(alpha), reinterpret_cast<const double2*>(beta),
+                                       nrows, nv, partial);
                 finalize(partial, 2, nv, rp, st);
                 return DIRAC_OK;
             });

@@ -5,6 +5,20 @@
 
 namespace dirac {
 
+// Solver epilogue of a row-tiled stencil launch (Wilson, staggered; the CG iteration on D^+ D):
+//   mode 1: the output is written as usual and each tile also writes the per-RHS sums of |out|^2 of its
+//           sites (values as stored) to partial[tile * nv + rhs];
+//   mode 2: the output q is not written: r -= alpha q (alpha: 2 nv doubles, complex, device; q as it would
+//           have been stored; r in FP64 for FP64 applies, FP32 otherwise) and the tile writes the per-RHS
+//           sums of |r|^2 (r as stored) to partial[tile * nv + rhs].
+// Tiles are x-rows: V / N_x of them.
+struct Epilogue {
+    int mode = 0;
+    double* partial = nullptr;
+    void* r = nullptr;
+    const double* alpha = nullptr;
+};
+
 struct StencilArgs {
     dirac_prec prec;
     int nc;
@@ -19,7 +33,12 @@ struct StencilArgs {
     void* out;
     const void* clover = nullptr;  // packed clover blocks (clover.h) for Wilson / Brillouin, or none
     bool laplace = false;          // the spin-trivial Laplace operator of the same stencil
+    Epilogue epi;                  // solver epilogue (row tiles of Wilson and staggered only)
 };
+
+// Return value of the launchers when an epilogue was asked for but the launch shape cannot apply it
+// (nothing was launched; the caller runs the unfused sequence).
+constexpr int kNoEpilogue = 100;
 
 // Stencil launches (asynchronous; arguments already validated).
 int launch_wilson(const StencilArgs& a, hipStream_t st);
@@ -39,7 +58,8 @@ inline bool op_takes_clover(dirac_op op) { return op == DIRAC_WILSON || op == DI
 // Launch one apply of `op` (D, D^+ with dag; the Laplacians ignore dag); rb and variant from the defaults
 // or the dirac_set_launch_shape overrides.
 int launch_stencil(dirac_op op, dirac_prec prec, int nc, int nv, const Geom& g, double mass, const void* gauge,
-                   const void* clover, const void* in, void* out, bool dag, hipStream_t st);
+                   const void* clover, const void* in, void* out, bool dag, hipStream_t st,
+                   const Epilogue& epi = Epilogue());
 int launch_force(dirac_op op, int nc, int nv, const Geom& g, const void* U, const void* psi, const void* chi,
                  void* gout, double coeff, hipStream_t st);
 int launch_project_su(int nc, int64_t nlinks, const void* U, const void* g, void* F, hipStream_t st);
@@ -61,6 +81,9 @@ constexpr int kReduceThreads = 256;
 inline size_t reduce_partial_doubles(int nv) { return static_cast<size_t>(kReduceBlocks) * 2 * nv; }
 
 int blas_norm2(dirac_prec p, const void* x, int64_t nrows, int nv, double* partial, double* out, hipStream_t st);
+// out[rhs] = sum over nblk blocks of partial[b * nv + rhs] (fixed order), e.g. the per-tile partials
+// of a stencil epilogue
+void finalize_blocks(const double* partial, int64_t nblk, int nv, double* out, hipStream_t st);
 // Device address of the library's own reduction partials on the current device (found once per
 // device); static_scratch_doubles() doubles, enough for reduce_partial_doubles(256).
 int static_scratch(double** out);

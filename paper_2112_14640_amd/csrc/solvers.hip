@@ -60,8 +60,9 @@ struct Field {
 
 size_t vec_bytes(const OpCtx& o, dirac_prec p) { return o.ncomplex() * complex_bytes(p); }
 
-int apply_op(const OpCtx& o, dirac_prec p, const Field& f, const void* in, void* out, bool dag, hipStream_t st) {
-    return launch_stencil(o.op, p, o.nc, o.nv, o.g, o.mass, f.gauge, f.clov, in, out, dag, st);
+int apply_op(const OpCtx& o, dirac_prec p, const Field& f, const void* in, void* out, bool dag, hipStream_t st,
+             const Epilogue& epi = Epilogue()) {
+    return launch_stencil(o.op, p, o.nc, o.nv, o.g, o.mass, f.gauge, f.clov, in, out, dag, st, epi);
 }
 
 // out = A in with A = D^+ D via tmp (A = D for the hermitian Laplacians; tmp unused)
@@ -129,9 +130,13 @@ struct Scalars {
     double* cplx = nullptr;     // 8nv general complex scratch (BiCGstab)
     double* mask = nullptr;     // nv (1 active, 0 frozen)
     double* rp = nullptr;       // 2nv: <r, p> (reliable-update line search)
+    double* tiles = nullptr;    // ntiles * nv: per-tile partial sums of the stencil epilogues
+    int64_t ntiles = 0;
     double* hbuf = nullptr;     // pinned host, 16 nv doubles
-    void carve(Carver& c, int nv_) {
+    void carve(Carver& c, int nv_, int64_t ntiles_) {
         nv = nv_;
+        ntiles = ntiles_;
+        tiles = static_cast<double*>(c.take(static_cast<size_t>(ntiles) * nv * sizeof(double)));
         partial = static_cast<double*>(c.take(reduce_partial_doubles(nv) * sizeof(double)));
         rr = static_cast<double*>(c.take(nv * sizeof(double)));
         rr_new = static_cast<double*>(c.take(nv * sizeof(double)));
@@ -220,6 +225,31 @@ int p_a_p(const OpCtx& o, dirac_prec pp, const void* p, const void* q, const voi
     return blas_norm2(pp, t, o.nrows, o.nv, partial, pq, st);
 }
 
+// The operator part of one CG step on A = D^+ D with the BLAS folded into the stencil epilogues:
+// t = D p with the tiles' sums of |t|^2 (-> s.pq), the step length from `alpha_kernel`, then
+// r -= alpha D^+ t with the tiles' sums of |r|^2 (-> s.rr_new); q = A p is never written.  kNoEpilogue
+// (nothing launched) when the shape has no fused form: the caller then runs the separate kernels.
+template <typename AlphaFn>
+int fused_normal_step(const OpCtx& o, dirac_prec pp, const Field& f, const void* p, void* t, void* q, dirac_prec pr,
+                      void* r, Scalars& s, AlphaFn&& alpha_kernel, hipStream_t st) {
+    if (o.hermitian() || (pp == DIRAC_FP64) != (pr == DIRAC_FP64) || !s.tiles) return kNoEpilogue;
+    Epilogue e1;
+    e1.mode = 1;
+    e1.partial = s.tiles;
+    int rc = apply_op(o, pp, f, p, t, false, st, e1);
+    if (rc) return rc;
+    finalize_blocks(s.tiles, s.ntiles, o.nv, s.pq, st);
+    alpha_kernel();
+    Epilogue e2;
+    e2.mode = 2;
+    e2.partial = s.tiles;
+    e2.r = r;
+    e2.alpha = s.alpha;
+    if ((rc = apply_op(o, pp, f, t, q, true, st, e2))) return rc;
+    finalize_blocks(s.tiles, s.ntiles, o.nv, s.rr_new, st);
+    return DIRAC_OK;
+}
+
 // ---------------------------------------------------------------------------
 // CG core on A = D^+ D.  Vectors: x (px), r (pr), p, q, t (pp); b (pb); operator in pp.
 // ---------------------------------------------------------------------------
@@ -277,11 +307,18 @@ int cg_core(const OpCtx& o, const CGVecs& v, const Rules& ru, Scalars& s, hipStr
             break;
         }
         ++it;
-        if ((rc = apply_normal(o, v.pp, v.f, v.p, v.q, v.t, st))) return rc;
-        int pstride;
-        if ((rc = p_a_p(o, v.pp, v.p, v.q, v.t, s.partial, s.pq, pstride, st))) return rc;
-        hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, st, s.pq, pstride, s.rr, s.mask, s.alpha, nv);
-        if ((rc = fused_r_update(v.pr, v.r, v.pp, v.q, s.alpha, o.nrows, nv, s.partial, s.rr_new, st))) return rc;
+        rc = fused_normal_step(o, v.pp, v.f, v.p, v.t, v.q, v.pr, v.r, s, [&]() {
+            hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, st, s.pq, 1, s.rr, s.mask, s.alpha, nv);
+        }, st);
+        if (rc == kNoEpilogue) {
+            if ((rc = apply_normal(o, v.pp, v.f, v.p, v.q, v.t, st))) return rc;
+            int pstride;
+            if ((rc = p_a_p(o, v.pp, v.p, v.q, v.t, s.partial, s.pq, pstride, st))) return rc;
+            hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, st, s.pq, pstride, s.rr, s.mask, s.alpha, nv);
+            if ((rc = fused_r_update(v.pr, v.r, v.pp, v.q, s.alpha, o.nrows, nv, s.partial, s.rr_new, st))) return rc;
+        } else if (rc) {
+            return rc;
+        }
         if ((rc = d2h(h, s.rr_new, nv, st))) return rc;
         std::vector<double> rn(h, h + nv);
         if (!all_finite(rn)) return fail(DIRAC_ENONFINITE, "non-finite residual norm during CG");
@@ -427,11 +464,19 @@ int cg_reliable(const OpCtx& o, const RUVecs& v, const Rules& ru, double delta, 
             break;
         }
         ++it;
-        if ((rc = apply_normal(o, v.pin, v.f_lo, v.p, v.q, v.t, st))) return rc;
-        int pstride;
-        if ((rc = p_a_p(o, v.pin, v.p, v.q, v.t, s.partial, s.pq, pstride, st))) return rc;
-        hipLaunchKernelGGL(k_cg_alpha_ls, dim3(1), dim3(256), 0, st, s.pq, pstride, s.rp, s.mask, s.alpha, nv);
-        if ((rc = fused_r_update(F32, v.r, v.pin, v.q, s.alpha, o.nrows, nv, s.partial, s.rr_new, st))) return rc;
+        rc = fused_normal_step(o, v.pin, v.f_lo, v.p, v.t, v.q, F32, v.r, s, [&]() {
+            hipLaunchKernelGGL(k_cg_alpha_ls, dim3(1), dim3(256), 0, st, s.pq, 1, s.rp, s.mask, s.alpha, nv);
+        }, st);
+        if (rc == kNoEpilogue) {
+            if ((rc = apply_normal(o, v.pin, v.f_lo, v.p, v.q, v.t, st))) return rc;
+            int pstride;
+            if ((rc = p_a_p(o, v.pin, v.p, v.q, v.t, s.partial, s.pq, pstride, st))) return rc;
+            hipLaunchKernelGGL(k_cg_alpha_ls, dim3(1), dim3(256), 0, st, s.pq, pstride, s.rp, s.mask, s.alpha, nv);
+            if ((rc = fused_r_update(F32, v.r, v.pin, v.q, s.alpha, o.nrows, nv, s.partial, s.rr_new, st)))
+                return rc;
+        } else if (rc) {
+            return rc;
+        }
         if ((rc = d2h(h, s.rr_new, nv, st))) return rc;
         std::vector<double> rn(h, h + nv);
         if (!all_finite(rn)) return fail(DIRAC_ENONFINITE, "non-finite inner residual norm");
@@ -846,7 +891,7 @@ size_t solver_workspace_bytes(dirac_op op, int solver, dirac_prec outer, dirac_p
     Layout l = layout_for(solver, outer, inner, scheme);
     Carver c{nullptr, 0};
     Scalars s;
-    s.carve(c, nv);
+    s.carve(c, nv, g.vol / g.nx);
     for (int i = 0; i < l.n_out; ++i) c.take(vec_bytes(o, outer));
     for (int i = 0; i < l.n_hi; ++i) c.take(vec_bytes(o, DIRAC_FP64));
     for (int i = 0; i < l.n_f32; ++i) c.take(vec_bytes(o, DIRAC_FP32));
@@ -870,7 +915,7 @@ int run_solver(int solver, dirac_op op, dirac_prec outer, dirac_prec inner, cons
     if (mis) base += kAlign - mis;
     Carver c{base, ws_bytes};
     Scalars s;
-    s.carve(c, nv);
+    s.carve(c, nv, g.vol / g.nx);
     const bool mixed = inner != outer;
     Rules ru;
     ru.tol = tol;

@@ -105,7 +105,7 @@ template <int NC, int RB, bool DAG, class P, typename Unit, bool LL>
 __global__ __launch_bounds__(512) void staggered_rows_kernel(const typename P::G* __restrict__ U,
                                                              const typename P::S* __restrict__ in,
                                                              typename P::S* __restrict__ out, typename P::R mass,
-                                                             Geom g, int nv, RowTile rt, int lap) {
+                                                             Geom g, int nv, RowTile rt, int lap, Epilogue epi) {
     using R = typename P::R;
     using S = typename P::S;
     using G = typename P::G;
@@ -275,6 +275,11 @@ __global__ __launch_bounds__(512) void staggered_rows_kernel(const typename P::G
     step(std::integral_constant<int, 2>{}, std::true_type{});
     step(std::integral_constant<int, 3>{}, std::false_type{});
     step(std::integral_constant<int, 3>{}, std::true_type{});
+    if (epi.mode == 2) {  // r -= alpha (D^+ t): the output itself is not written
+        row_epilogue<RB, NC, R, S>(epi, acc, active, site * (NC * nv) + rg * RB, nv, rg * RB, j, rt.S, tix,
+                                   reinterpret_cast<double*>(sraw));
+        return;
+    }
     __syncthreads();
     if (active) {
         S* o = const_cast<S*>(at(j));
@@ -290,6 +295,8 @@ __global__ __launch_bounds__(512) void staggered_rows_kernel(const typename P::G
     // displace input rows that neighbouring work-groups still read from L2
     for (uint32_t u = tid; u < total; u += blockDim.x)
         __builtin_nontemporal_store(rtile[u + fast_div(u, rt.magic_units)], dst + u);
+    if (epi.mode == 1)
+        row_epilogue<RB, NC, R, S>(epi, acc, active, 0, nv, rg * RB, j, rt.S, tix, reinterpret_cast<double*>(sraw));
 }
 
 template <int NC, int RB, class P>
@@ -337,28 +344,30 @@ bool launch_rows(const StencilArgs& a, int nv, typename P::R diag, hipStream_t s
         if (ll) {
             if (a.dagger)
                 hipLaunchKernelGGL((staggered_rows_kernel<NC, RB, true, P, Unit, true>), grid, dim3(block), lds_ll, st,
-                                   U, in, out, diag, a.g, nv, rt, lap);
+                                   U, in, out, diag, a.g, nv, rt, lap, a.epi);
             else
                 hipLaunchKernelGGL((staggered_rows_kernel<NC, RB, false, P, Unit, true>), grid, dim3(block), lds_ll, st,
-                                   U, in, out, diag, a.g, nv, rt, lap);
+                                   U, in, out, diag, a.g, nv, rt, lap, a.epi);
         } else if (a.dagger) {
             hipLaunchKernelGGL((staggered_rows_kernel<NC, RB, true, P, Unit, false>), grid, dim3(block), lds, st, U, in,
-                               out, diag, a.g, nv, rt, lap);
+                               out, diag, a.g, nv, rt, lap, a.epi);
         } else {
             hipLaunchKernelGGL((staggered_rows_kernel<NC, RB, false, P, Unit, false>), grid, dim3(block), lds, st, U,
-                               in, out, diag, a.g, nv, rt, lap);
+                               in, out, diag, a.g, nv, rt, lap, a.epi);
         }
         return true;
     }
 }
 
+// false: an epilogue was asked for and only the direct kernel could take this shape (nothing launched)
 template <int NC, int RB, class P>
-void launch_rb(const StencilArgs& a, hipStream_t st) {
+bool launch_rb(const StencilArgs& a, hipStream_t st) {
     using R = typename P::R;
     // the Wilson Laplacian treats the spin index as four more columns per colour
     const int nv = a.laplace ? 4 * a.nv : a.nv;
     const R diag = static_cast<R>(a.laplace ? 4.0 + 0.5 * a.mass * a.mass : a.mass);
-    if (a.variant == 4 && launch_rows<NC, RB, P>(a, nv, diag, st)) return;
+    if (a.variant == 4 && launch_rows<NC, RB, P>(a, nv, diag, st)) return true;
+    if (a.epi.mode != 0) return false;
     const int block = 256;
     const int64_t threads = a.g.vol * (nv / RB);
     const dim3 grid(static_cast<unsigned>(grid_blocks_x8(threads, block)));
@@ -373,27 +382,29 @@ void launch_rb(const StencilArgs& a, hipStream_t st) {
     else
         hipLaunchKernelGGL((staggered_kernel<NC, RB, false, P>), grid, dim3(block), 0, st, U, in, out, diag, a.g, nv,
                            ord, lap);
+    return true;
 }
 
 template <int NC, class P>
-void launch_nc(const StencilArgs& a, hipStream_t st) {
+bool launch_nc(const StencilArgs& a, hipStream_t st) {
     switch (a.rb) {
-        case 4: launch_rb<NC, 4, P>(a, st); break;
-        case 2: launch_rb<NC, 2, P>(a, st); break;
-        default: launch_rb<NC, 1, P>(a, st); break;
+        case 4: return launch_rb<NC, 4, P>(a, st);
+        case 2: return launch_rb<NC, 2, P>(a, st);
+        default: return launch_rb<NC, 1, P>(a, st);
     }
 }
 
 template <class P>
 int launch_prec(const StencilArgs& a, hipStream_t st) {
+    bool ok;
     switch (a.nc) {
-        case 1: launch_nc<1, P>(a, st); break;
-        case 2: launch_nc<2, P>(a, st); break;
-        case 3: launch_nc<3, P>(a, st); break;
-        case 4: launch_nc<4, P>(a, st); break;
+        case 1: ok = launch_nc<1, P>(a, st); break;
+        case 2: ok = launch_nc<2, P>(a, st); break;
+        case 3: ok = launch_nc<3, P>(a, st); break;
+        case 4: ok = launch_nc<4, P>(a, st); break;
         default: return DIRAC_EUNSUPPORTED;
     }
-    return DIRAC_OK;
+    return ok ? DIRAC_OK : kNoEpilogue;
 }
 
 }  // namespace

@@ -2,6 +2,8 @@
 // buffer loads that copy whole x-rows of the lattice into LDS.
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -185,6 +187,67 @@ bool allow_lds(K kernel, size_t lds) {
     if (lds <= 64 * 1024) return true;
     return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
                                static_cast<int>(kRowLdsCap)) == hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// Solver epilogue of the row kernels (see Epilogue in kernels.h).  acc[k][e] is the thread's output
+// for right-hand side rhs0 + k and element e (element e of a site block at offset e * nv); elem0 is the
+// index of the thread's first element in the vector.  Each tile writes nv per-RHS sums, reduced over
+// its sites in a fixed order through `red` (LDS, at least sites * nv doubles, free when called).
+// ---------------------------------------------------------------------------
+template <typename R, typename S>
+__device__ __forceinline__ cx<R> as_stored(cx<R> v) {
+    S t;
+    io<R, S>::st(&t, v);
+    return io<R, S>::ld(&t);
+}
+
+template <int RB, int NE, typename R, typename S>
+__device__ __forceinline__ void row_epilogue(const Epilogue& epi, const cx<R> (&acc)[RB][NE], bool active,
+                                             int64_t elem0, int nv, int rhs0, uint32_t j, int sites, int64_t tile,
+                                             double* red) {
+    using RS = std::conditional_t<sizeof(R) == 8, double2, float2>;  // the residual's storage
+    double sq[RB];
+#pragma unroll
+    for (int k = 0; k < RB; ++k) sq[k] = 0.0;
+    if (active) {
+        if (epi.mode == 2) {
+            RS* r = static_cast<RS*>(epi.r) + elem0;
+            const double2* al = reinterpret_cast<const double2*>(epi.alpha) + rhs0;
+#pragma unroll
+            for (int k = 0; k < RB; ++k) {
+                const double2 a = al[k];
+                const cx<double> ma{-a.x, -a.y};
+#pragma unroll
+                for (int e = 0; e < NE; ++e) {
+                    const cx<R> q = as_stored<R, S>(acc[k][e]);
+                    cx<double> rv = io<double, RS>::ld(r + e * nv + k);
+                    cfma(rv, ma, cx<double>{static_cast<double>(q.re), static_cast<double>(q.im)});
+                    io<double, RS>::st(r + e * nv + k, rv);
+                    const cx<double> sv = io<double, RS>::ld(r + e * nv + k);
+                    sq[k] += sv.re * sv.re + sv.im * sv.im;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < RB; ++k)
+#pragma unroll
+                for (int e = 0; e < NE; ++e) {
+                    const cx<R> v = as_stored<R, S>(acc[k][e]);
+                    sq[k] += static_cast<double>(v.re) * v.re + static_cast<double>(v.im) * v.im;
+                }
+        }
+    }
+    __syncthreads();  // red may alias the row tile
+    if (active)
+#pragma unroll
+        for (int k = 0; k < RB; ++k) red[j * nv + rhs0 + k] = sq[k];
+    __syncthreads();
+    if (threadIdx.x < static_cast<uint32_t>(nv)) {
+        double t = 0.0;
+        for (int jj = 0; jj < sites; ++jj) t += red[jj * nv + threadIdx.x];
+        epi.partial[tile * nv + threadIdx.x] = t;
+    }
 }
 
 inline bool tile_aligned(const StencilArgs& a) {

@@ -280,7 +280,7 @@ __global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* _
                                                           const typename P::S* __restrict__ in,
                                                           typename P::S* __restrict__ out, typename P::R diag,
                                                           Geom g, int nv, RowTile rt,
-                                                          const typename P::R* __restrict__ clov) {
+                                                          const typename P::R* __restrict__ clov, Epilogue epi) {
     using R = typename P::R;
     using S = typename P::S;
     constexpr int PER = RowUnits<NC, RB, P>::PER;
@@ -443,6 +443,13 @@ __global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* _
     step(std::integral_constant<int, 2>{}, std::true_type{});
     step(std::integral_constant<int, 3>{}, std::false_type{});
     step(std::integral_constant<int, 3>{}, std::true_type{});
+    // the thread's outputs as [RB][NC * 4] (element a * 4 + s at offset (a * 4 + s) * nv)
+    const auto& flat = reinterpret_cast<const cx<R>(&)[RB][NC * 4]>(acc);
+    if (epi.mode == 2) {  // r -= alpha (D^+ t): the output itself is not written
+        row_epilogue<RB, NC * 4, R, S>(epi, flat, active, site * (NC * 4 * nv) + rg * RB, nv, rg * RB, j, rt.S, tix,
+                                       reinterpret_cast<double*>(rtile));
+        return;
+    }
     __syncthreads();
     if (active) {
         S* o = const_cast<S*>(at(j));
@@ -461,6 +468,9 @@ __global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* _
     // displace input rows that neighbouring work-groups still read from L2
     for (uint32_t u = tid; u < total; u += blockDim.x)
         __builtin_nontemporal_store(rtile[u + fast_div(u, rt.magic_units)], dst + u);
+    if (epi.mode == 1)
+        row_epilogue<RB, NC * 4, R, S>(epi, flat, active, 0, nv, rg * RB, j, rt.S, tix,
+                                       reinterpret_cast<double*>(rtile));
 }
 
 template <int NC, int RB, class P>
@@ -507,7 +517,7 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
             ok = false;
             return;
         }
-        hipLaunchKernelGGL(kern, grid, dim3(block), lds, st, U, in, out, diag, a.g, a.nv, rt, clov);
+        hipLaunchKernelGGL(kern, grid, dim3(block), lds, st, U, in, out, diag, a.g, a.nv, rt, clov, a.epi);
     };
     // the clover term is a separate instantiation: its registers would otherwise lower the occupancy
     // of the plain kernel
@@ -536,10 +546,12 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
     return ok;
 }
 
+// false: an epilogue was asked for and only the direct kernel could take this shape (nothing launched)
 template <int NC, int RB, class P>
-void launch_rb(const StencilArgs& a, hipStream_t st) {
+bool launch_rb(const StencilArgs& a, hipStream_t st) {
     using R = typename P::R;
-    if (a.variant == 4 && launch_rows<NC, RB, P>(a, st)) return;
+    if (a.variant == 4 && launch_rows<NC, RB, P>(a, st)) return true;
+    if (a.epi.mode != 0) return false;
     // direct loads (selected, or the row tile does not fit this shape)
     const int block = 256;
     const int64_t threads = a.g.vol * (a.nv / RB);
@@ -556,26 +568,25 @@ void launch_rb(const StencilArgs& a, hipStream_t st) {
     else
         hipLaunchKernelGGL((wilson_kernel<NC, RB, false, P>), grid, dim3(block), 0, st, U, in, out, diag, a.g, a.nv,
                            ord, clov);
+    return true;
 }
 
 template <int NC, class P>
-void launch_nc(const StencilArgs& a, hipStream_t st) {
-    if (a.rb == 2)
-        launch_rb<NC, 2, P>(a, st);
-    else
-        launch_rb<NC, 1, P>(a, st);
+bool launch_nc(const StencilArgs& a, hipStream_t st) {
+    return a.rb == 2 ? launch_rb<NC, 2, P>(a, st) : launch_rb<NC, 1, P>(a, st);
 }
 
 template <class P>
 int launch_prec(const StencilArgs& a, hipStream_t st) {
+    bool ok;
     switch (a.nc) {
-        case 1: launch_nc<1, P>(a, st); break;
-        case 2: launch_nc<2, P>(a, st); break;
-        case 3: launch_nc<3, P>(a, st); break;
-        case 4: launch_nc<4, P>(a, st); break;
+        case 1: ok = launch_nc<1, P>(a, st); break;
+        case 2: ok = launch_nc<2, P>(a, st); break;
+        case 3: ok = launch_nc<3, P>(a, st); break;
+        case 4: ok = launch_nc<4, P>(a, st); break;
         default: return DIRAC_EUNSUPPORTED;
     }
-    return DIRAC_OK;
+    return ok ? DIRAC_OK : kNoEpilogue;
 }
 
 }  // namespace
