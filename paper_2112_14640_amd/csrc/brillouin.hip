@@ -51,86 +51,139 @@ __device__ __forceinline__ const double* spin_table<double>(int dag, int flip, i
 }
 
 // ---------------------------------------------------------------------------
-// Link construction: one thread per (stored direction, site); direction is the slow
-// index so that a wavefront shares one direction (uniform loop counts).
+// Link construction, level by level.  Grouping the |d|! orderings of the unit steps of d by
+// their last step gives
+//     W_d(n) = (1/|d|) sum_{mu: d_mu != 0} W_{d - s e_mu}(n) L,   s = d_mu,
+// with L = V_mu(n + d - e_mu) for s = +1 and L = V_mu(n + d)^+ for s = -1: the average at
+// |d| is built from the averages at |d| - 1 of the same site, so a site needs 176 products
+// (levels 2, 3 in all 56 directions and the 8 stored ones of level 4) instead of the 1108 of
+// the separate paths.  A work-group takes S consecutive sites, holds the levels of its
+// sites in LDS (slot = direction number; in the output precision, products accumulated in
+// FP64), and writes each site's 40 stored directions as one contiguous block.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool next_perm(int* a, int k) {
-    int i = k - 2;
-    while (i >= 0 && a[i] >= a[i + 1]) --i;
-    if (i < 0) return false;
-    int j = k - 1;
-    while (a[j] <= a[i]) --j;
-    int t = a[i];
-    a[i] = a[j];
-    a[j] = t;
-    for (int l = i + 1, r = k - 1; l < r; ++l, --r) {
-        t = a[l];
-        a[l] = a[r];
-        a[r] = t;
-    }
-    return true;
+struct LevelDirs {
+    unsigned char dir[64];  // level 2 (24 directions), level 3 (32), level 4 stored (8)
+};
+constexpr LevelDirs make_level_dirs() {
+    LevelDirs l{};
+    int n = 0;
+    for (int k = 2; k <= 4; ++k)
+        for (int dir = 0; dir < 81; ++dir) {
+            int nz = 0;
+            for (int mu = 0, q = dir; mu < 4; ++mu, q /= 3) nz += q % 3 != 1;
+            if (nz == k && (k < 4 || dir < 40)) l.dir[n++] = static_cast<unsigned char>(dir);
+        }
+    return l;
 }
+__constant__ LevelDirs c_levels = make_level_dirs();
+constexpr int kLevelStart[3] = {0, 24, 56};
+constexpr int kLevelCount[3] = {24, 32, 8};
+constexpr int kDirStride[4] = {1, 3, 9, 27};
+
+template <int NC>
+constexpr int link_tile_sites() {
+    return NC <= 3 ? 4 : 2;  // 4 x 81 x 9 x 16 B = 46.7 KB of LDS for N_c = 3 in FP64, half in FP32
+}
+constexpr int kLinkThreads = 128;
 
 template <int NC, typename GI, typename GO>
-__global__ __launch_bounds__(256) void links_kernel(const GI* __restrict__ U, GO* __restrict__ W, Geom g) {
-    const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (gid >= 40 * g.vol) return;
-    const int dir = static_cast<int>(gid / g.vol);
-    const int64_t site = gid - static_cast<int64_t>(dir) * g.vol;
-    const int d[4] = {dir % 3 - 1, (dir / 3) % 3 - 1, (dir / 9) % 3 - 1, dir / 27 - 1};
-    int smu[4], ssg[4], k = 0;
-    for (int mu = 0; mu < 4; ++mu)
-        if (d[mu] != 0) {
-            smu[k] = mu;
-            ssg[k] = d[mu];
-            ++k;
-        }
-    const Coord c0 = site_coord(site, g);
+__global__ __launch_bounds__(kLinkThreads) void links_kernel(const GI* __restrict__ U, GO* __restrict__ W, Geom g) {
+    constexpr int S = link_tile_sites<NC>();
+    constexpr int L = NC * NC;
+    using T = std::conditional_t<sizeof(GO) == 8, float, double>;
+    __shared__ cx<T> lw[S][81][L];
+    const int64_t site0 = logical_block() * S;
+    if (site0 >= g.vol) return;
+    const int ns = static_cast<int>(g.vol - site0 < S ? g.vol - site0 : S);
+    const int tid = threadIdx.x;
     const int ext[4] = {g.nx, g.ny, g.nz, g.nt};
-
-    cx<double> acc[NC][NC];
-    for (int a = 0; a < NC; ++a)
-        for (int b = 0; b < NC; ++b) acc[a][b] = {0.0, 0.0};
-    int perm[4] = {0, 1, 2, 3};
-    int npaths = 0;
-    do {
-        int x[4] = {c0.x, c0.y, c0.z, c0.t};
-        cx<double> p[NC][NC];
-        for (int a = 0; a < NC; ++a)
-            for (int b = 0; b < NC; ++b) p[a][b] = {a == b ? 1.0 : 0.0, 0.0};
-        for (int j = 0; j < k; ++j) {
-            const int mu = smu[perm[j]];
-            const int sg = ssg[perm[j]];
-            cx<double> l[NC][NC];
-            if (sg > 0) {
-                const GI* lp = U + (site_index(x[0], x[1], x[2], x[3], g) * 4 + mu) * NC * NC;
-                for (int a = 0; a < NC; ++a)
-                    for (int b = 0; b < NC; ++b) l[a][b] = io<double, GI>::ld(lp + a * NC + b);
-                x[mu] = wrap(x[mu] + 1, ext[mu]);
-            } else {
-                x[mu] = wrap(x[mu] - 1, ext[mu]);
-                const GI* lp = U + (site_index(x[0], x[1], x[2], x[3], g) * 4 + mu) * NC * NC;
-                for (int a = 0; a < NC; ++a)
-                    for (int b = 0; b < NC; ++b) l[b][a] = cconj(io<double, GI>::ld(lp + a * NC + b));
-            }
-            cx<double> q[NC][NC];
-            for (int a = 0; a < NC; ++a)
-                for (int b = 0; b < NC; ++b) {
-                    cx<double> s{0.0, 0.0};
-                    for (int e = 0; e < NC; ++e) cfma(s, p[a][e], l[e][b]);
-                    q[a][b] = s;
-                }
-            for (int a = 0; a < NC; ++a)
-                for (int b = 0; b < NC; ++b) p[a][b] = q[a][b];
+    auto link_at = [&](const int* c, int mu) __attribute__((always_inline)) {
+        return U + (site_index(c[0], c[1], c[2], c[3], g) * 4 + mu) * L;
+    };
+    // level 1: W_{+e_mu}(n) = V_mu(n), W_{-e_mu}(n) = V_mu(n - e_mu)^+
+    for (int u = tid; u < ns * 8 * L; u += kLinkThreads) {
+        const int s = u / (8 * L), j = (u / L) % 8, e = u % L;
+        const int mu = j >> 1, a = e / NC, b = e % NC;
+        const Coord c0 = site_coord(site0 + s, g);
+        int c[4] = {c0.x, c0.y, c0.z, c0.t};
+        if (j & 1) {
+            c[mu] = wrap(c[mu] - 1, ext[mu]);
+            lw[s][40 - kDirStride[mu]][e] = cconj(io<T, GI>::ld(link_at(c, mu) + b * NC + a));
+        } else {
+            lw[s][40 + kDirStride[mu]][e] = io<T, GI>::ld(link_at(c, mu) + e);
         }
-        for (int a = 0; a < NC; ++a)
-            for (int b = 0; b < NC; ++b) acc[a][b] = cadd(acc[a][b], p[a][b]);
-        ++npaths;
-    } while (next_perm(perm, k));
-    const double inv = 1.0 / npaths;
-    GO* out = W + (site * 40 + dir) * NC * NC;
-    for (int a = 0; a < NC; ++a)
-        for (int b = 0; b < NC; ++b) io<double, GO>::st(out + a * NC + b, cscale(inv, acc[a][b]));
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int lev = 0; lev < 3; ++lev) {
+        const int k = lev + 2, cnt = kLevelCount[lev];
+        const double inv = 1.0 / k;
+        for (int u = tid; u < ns * cnt; u += kLinkThreads) {
+            const int s = u / cnt;
+            const int dir = c_levels.dir[kLevelStart[lev] + (u - s * cnt)];
+            const Coord c0 = site_coord(site0 + s, g);
+            const int n0[4] = {c0.x, c0.y, c0.z, c0.t};
+            int d[4];
+            for (int mu = 0, q = dir; mu < 4; ++mu, q /= 3) d[mu] = q % 3 - 1;
+            // the links of all last steps are loaded before any product, so their latencies overlap
+            GI raw[4][L];
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu) {
+                if (d[mu] == 0) continue;
+                int c[4];
+#pragma unroll
+                for (int nu = 0; nu < 4; ++nu)
+                    c[nu] = wrap(n0[nu] + d[nu] - (nu == mu && d[mu] > 0 ? 1 : 0), ext[nu]);
+                const GI* lp = link_at(c, mu);
+#pragma unroll
+                for (int e = 0; e < L; ++e) raw[mu][e] = lp[e];
+            }
+            cx<double> acc[NC][NC];
+#pragma unroll
+            for (int a = 0; a < NC; ++a)
+#pragma unroll
+                for (int b = 0; b < NC; ++b) acc[a][b] = {0.0, 0.0};
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu) {
+                if (d[mu] == 0) continue;
+                const int sg = d[mu];
+                const cx<T>* prev = lw[s][dir - sg * kDirStride[mu]];
+                cx<double> l[NC][NC];
+#pragma unroll
+                for (int a = 0; a < NC; ++a)
+#pragma unroll
+                    for (int b = 0; b < NC; ++b) {
+                        const cx<double> v = io<double, GI>::ld(&raw[mu][a * NC + b]);
+                        if (sg > 0)
+                            l[a][b] = v;
+                        else
+                            l[b][a] = cconj(v);
+                    }
+#pragma unroll
+                for (int a = 0; a < NC; ++a)
+#pragma unroll
+                    for (int e = 0; e < NC; ++e) {
+                        const cx<double> pv{prev[a * NC + e].re, prev[a * NC + e].im};
+#pragma unroll
+                        for (int b = 0; b < NC; ++b) cfma(acc[a][b], pv, l[e][b]);
+                    }
+            }
+#pragma unroll
+            for (int a = 0; a < NC; ++a)
+#pragma unroll
+                for (int b = 0; b < NC; ++b) {
+                    const cx<double> v = cscale(inv, acc[a][b]);
+                    lw[s][dir][a * NC + b] = {static_cast<T>(v.re), static_cast<T>(v.im)};
+                }
+        }
+        __syncthreads();
+    }
+    // the stored directions 0..39 of the tile's sites are one contiguous block of W
+    GO* out = W + site0 * 40 * L;
+    for (int u = tid; u < ns * 40 * L; u += kLinkThreads) {
+        const int s = u / (40 * L), r = u - s * 40 * L;
+        io<T, GO>::st(out + u, lw[s][r / L][r % L]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -634,14 +687,13 @@ int launch_prec(const StencilArgs& a, hipStream_t st) {
 
 template <int NC>
 void launch_links_nc(dirac_prec prec, const Geom& g, const void* U, void* W, hipStream_t st) {
-    const int block = 256;
-    const dim3 grid(static_cast<unsigned>((40 * g.vol + block - 1) / block));
+    const dim3 grid(static_cast<unsigned>(grid_blocks_x8(g.vol, link_tile_sites<NC>())));
     if (prec == DIRAC_FP64)
-        hipLaunchKernelGGL((links_kernel<NC, double2, double2>), grid, dim3(block), 0, st,
+        hipLaunchKernelGGL((links_kernel<NC, double2, double2>), grid, dim3(kLinkThreads), 0, st,
                            static_cast<const double2*>(U), static_cast<double2*>(W), g);
     else
-        hipLaunchKernelGGL((links_kernel<NC, float2, float2>), grid, dim3(block), 0, st, static_cast<const float2*>(U),
-                           static_cast<float2*>(W), g);
+        hipLaunchKernelGGL((links_kernel<NC, float2, float2>), grid, dim3(kLinkThreads), 0, st,
+                           static_cast<const float2*>(U), static_cast<float2*>(W), g);
 }
 
 }  // namespace
