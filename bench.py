@@ -171,21 +171,54 @@ def run_applies(args, torch, dirac, si):
                 link_build_ms=round(min(link_ms), 3), dims=dims, nc=nc, nv=nv)
 
 
-def run_ceilings(torch, dirac):
-    """The device's sustained copy bandwidth and non-packed FMA rates (the measured roofline denominators)."""
+def run_ceilings(torch):
+    """The device's sustained copy bandwidth and non-packed FMA rates (the measured roofline denominators), and
+    the rate of the stencils' seven-row gather pattern without arithmetic at the Wilson and staggered FP32 Nv = 12
+    site blocks (the ceiling of that access pattern through the caches)."""
+    from paper_2112_14640_amd import measure
+
     n = 2 ** 30 // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda:0")
     dst = torch.empty_like(src)
-    copy = dirac.probe_copy(src, dst, reps=10)
+    copy = measure.copy_rate(src, dst, reps=10)
     del src, dst
     torch.cuda.empty_cache()
-    out = {"copy_GBps": round(copy / 1e9, 1), "fp32_fma_TFLOPs": round(dirac.probe_fma("fp32") / 1e12, 2),
-           "fp64_fma_TFLOPs": round(dirac.probe_fma("fp64") / 1e12, 2),
-           "how": "dirac_probe_copy: 1 GiB device copy, 16 B per lane, 10 launches; dirac_probe_fma: 16 independent "
-                  "non-packed FMA chains per thread, 16 work-groups of 256 threads per CU"}
+    out = {"copy_GBps": round(copy / 1e9, 1), "fp32_fma_TFLOPs": round(measure.fma_rate("fp32") / 1e12, 2),
+           "fp64_fma_TFLOPs": round(measure.fma_rate("fp64") / 1e12, 2)}
+    gather, rowcopy = {}, {}
+    for name, dims, site_bytes in (("wilson_16x32", (16, 16, 16, 32), 1152), ("wilson_32x64", (32, 32, 32, 64), 1152),
+                                   ("staggered_16x32", (16, 16, 16, 32), 288),
+                                   ("staggered_48x96", (48, 48, 48, 96), 288)):
+        nbytes = dims[0] * dims[1] * dims[2] * dims[3] * site_bytes
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        gather[name] = round(measure.row_gather_rate(dims, site_bytes, a, b, reps=10) / 1e9, 1)
+        rowcopy[name] = round(measure.row_gather_rate(dims, site_bytes, a, b, reps=10, nrows=1) / 1e9, 1)
+        del a, b
+        torch.cuda.empty_cache()
+    out["row_gather_GBps"] = gather
+    out["row_copy_GBps"] = rowcopy
+    out["how"] = ("dirac_probe_copy: 1 GiB device copy, 16 B per lane, 10 launches; dirac_probe_fma: 16 independent "
+                  "non-packed FMA chains per thread, 16 work-groups of 256 threads per CU; dirac_probe_row_gather: one "
+                  "work-group per x-row reads its row and the +-y, +-z, +-t rows and writes one row, in the stencils' "
+                  "row order, rate = (read + write of one vector) / time (1152 B sites: Wilson, 288 B: staggered); row copy: the same "
+                  "kernel reading only its own row")
     log(f"[bench] ceilings: copy {out['copy_GBps']} GB/s, FMA fp32 {out['fp32_fma_TFLOPs']} / fp64 "
-        f"{out['fp64_fma_TFLOPs']} TFLOP/s")
+        f"{out['fp64_fma_TFLOPs']} TFLOP/s, row gather {gather} GB/s")
     return out
+
+
+def add_gather_fraction(r, op, nc, nv, vol, ceil, size):
+    """Spinor bytes (one read + one write of the vector, no links) per second against the measured rate of the
+    seven-row gather pattern at the same site block and lattice."""
+    key = f"{op}_{size}"
+    if key not in ceil.get("row_gather_GBps", {}):
+        return
+    spin = 1 if op == "staggered" else 4
+    gb = 2 * (2 * nc * spin * nv) * 4 * vol / (r["ms"] * 1e-3) / 1e9
+    r["spinor_GBps"] = round(gb, 1)
+    r["row_gather_ceiling_GBps"] = ceil["row_gather_GBps"][key]
+    r["frac_of_row_gather"] = round(gb / ceil["row_gather_GBps"][key], 4)
 
 
 def time_apply(torch, fn, reps):
@@ -223,6 +256,7 @@ def run_scale(torch, dirac, si, ceil):
             r.update(bound="hbm", achieved=round(gb, 1), unit="GB/s", frac=round(gb / HBM_PEAK_GBS, 4))
             if ceil:
                 r["frac_of_measured"] = round(gb / ceil["copy_GBps"], 4)
+                add_gather_fraction(r, op, nc, nv, vol, ceil, name.split("_")[1])
         out[name] = r
         log(f"[bench] scale {name}: {ms:.3f} ms, {r['achieved']} {r['unit']}")
 
@@ -511,6 +545,7 @@ def main():
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-scale", action="store_true", help="skip the large-lattice applies, BiCGstab and ceilings")
+    ap.add_argument("--ceilings", action="store_true", help="measure the ceilings even with --no-scale")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (outside the timed steps) whose HBM counters "
                          "scale the PMC byte counts of the stencil kernels")
@@ -539,12 +574,15 @@ def main():
         torch.cuda.synchronize()
         log("[bench] calibration copies done: 5 x 512 MiB read + 512 MiB write")
         del src, dst
-    ceil = None if args.no_scale else run_ceilings(torch, dirac)
+    ceil = run_ceilings(torch) if (args.ceilings or not args.no_scale) else None
     res = run_applies(args, torch, dirac, si)
     if ceil:
+        vol = res["dims"][0] * res["dims"][1] * res["dims"][2] * res["dims"][3]
         for name, r in res["rooflines"].items():
             r["frac_of_measured"] = round(r["achieved"] / (ceil["fp32_fma_TFLOPs"] if r["bound"] == "alu"
                                                            else ceil["copy_GBps"]), 4)
+            if r["bound"] == "hbm":
+                add_gather_fraction(r, name.split("_")[0], res["nc"], res["nv"], vol, ceil, "16x32")
     extras = None if args.no_scale else run_extras(torch, dirac, si)
     scale = None if args.no_scale else run_scale(torch, dirac, si, ceil)
     cg = None if args.no_cg else run_cg(torch, dirac, si)

@@ -288,19 +288,6 @@ int bicgstab_solve(dirac_op op, dirac_prec outer, dirac_prec inner, const void* 
  * cannot take.  Results agree to rounding whatever the shape.  Process-wide, not thread-safe. */
 int dirac_set_launch_shape(dirac_op op, dirac_prec prec, int rb, int variant);
 
-/* Measurement probes (not part of the method): the device's sustained rates, the measured
- * denominators next to the published peaks in the roofline figures.
- *   dirac_probe_copy: copies nbytes (a positive multiple of 16; both buffers 16-byte aligned,
- *     device, caller-owned, not overlapping) from src to dst reps times on the stream between two
- *     HIP events, one 16-byte load and store per lane, and returns (read + written bytes) / second.
- *   dirac_probe_fma: runs a register-resident loop of independent, non-packed fused multiply-adds
- *     (prec FP32 or FP64) over 16 work-groups per CU and returns flop/second (an FMA counts 2).
- *     sink: a device buffer of at least 8 bytes that the kernel may write (it never does for the
- *     inputs used; the write only keeps the loop alive).
- * Both synchronise with the stream.  EINVAL on bad arguments, EHIP on a HIP failure. */
-int dirac_probe_copy(const void* src, void* dst, size_t nbytes, int reps, double* bytes_per_s, void* stream);
-int dirac_probe_fma(dirac_prec prec, void* sink, double* flops_per_s, void* stream);
-
 /* Flop count per site and RHS of one apply, App. E convention (daggers count the same). */
 double dirac_flops_per_site(dirac_op op, int nc);
 

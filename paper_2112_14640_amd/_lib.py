@@ -81,8 +81,6 @@ SIGNATURES = {
     "bicgstab_solve": (_i, [_i, _i, _i, _vp, _vp, _vp, _vp, _d, _i, _i, _dims, _d, _i, _vp, _sz,
                             C.POINTER(SolveInfo), C.POINTER(SolveOpts), _vp]),
     "dirac_set_launch_shape": (_i, [_i, _i, _i, _i]),
-    "dirac_probe_copy": (_i, [_vp, _vp, _sz, _i, C.POINTER(C.c_double), _vp]),
-    "dirac_probe_fma": (_i, [_i, _vp, C.POINTER(C.c_double), _vp]),
     "dirac_flops_per_site": (_d, [_i, _i]),
     "dirac_error_string": (C.c_char_p, [_i]),
     "dirac_last_error": (C.c_char_p, []),

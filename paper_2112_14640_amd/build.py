@@ -3,7 +3,8 @@
     python -m paper_2112_14640_amd.build [--jobs N] [--verbose]
 
 Every ``csrc/*.hip`` file is compiled to an object under ``_build/`` with hipcc
-for gfx950 only, then linked into ``paper_2112_14640_amd/libdirac.so``.  The
+for gfx950 only, then linked into ``paper_2112_14640_amd/libdirac.so``; the
+measurement probes (``measure/probe.hip``) become ``measure/libdirac_probe.so``.  The
 build always recompiles (it is the "does it build" check); objects of
 unchanged sources are reused only when ``incremental=True``.
 """
@@ -22,6 +23,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libdirac.so")
+# measurement probes: a library of their own, sharing no code with the operator library
+PROBE_SRC = os.path.join(PKG, "measure", "probe.hip")
+PROBE_LIB = os.path.join(PKG, "measure", "libdirac_probe.so")
 ARCH = "gfx950"
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
@@ -40,8 +44,8 @@ COMMON_FLAGS = [
 ]
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src).replace(".hip", ".o"))
+def _compile(src: str, verbose: bool, obj: str | None = None) -> str:
+    obj = obj or os.path.join(BUILD, os.path.basename(src).replace(".hip", ".o"))
     cmd = [HIPCC, *COMMON_FLAGS, "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -80,7 +84,19 @@ def build(jobs: int | None = None, verbose: bool = False, incremental: bool = Fa
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stdout}\n{res.stderr}")
     os.replace(tmp, LIB)
+    _link(_compile(PROBE_SRC, verbose, os.path.join(BUILD, "measure_probe.o")), PROBE_LIB, verbose)
     return LIB
+
+
+def _link(obj: str, lib: str, verbose: bool) -> None:
+    tmp = lib + ".tmp"
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", obj, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"link failed:\n{res.stdout}\n{res.stderr}")
+    os.replace(tmp, lib)
 
 
 def main() -> None:

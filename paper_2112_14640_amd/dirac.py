@@ -543,27 +543,6 @@ def bicgstab(op, gauge, b, mass, x0=None, tol=1e-10, maxit=1000, inner=None, gau
                   opts, clover, clover_lo)
 
 
-def probe_copy(src: torch.Tensor, dst: torch.Tensor, reps: int = 10) -> float:
-    """Sustained device copy rate (read + written bytes per second) over src -> dst (same byte size)."""
-    _require(src, "src")
-    _require(dst, "dst", src.device)
-    nbytes = src.numel() * src.element_size()
-    if dst.numel() * dst.element_size() != nbytes:
-        raise ValueError("probe_copy: src and dst must have the same byte size")
-    out = C.c_double(0.0)
-    L.check(L.load().dirac_probe_copy(_ptr(src), _ptr(dst), nbytes, reps, C.byref(out), _stream()), "dirac_probe_copy")
-    return out.value
-
-
-def probe_fma(prec="fp32") -> float:
-    """Sustained non-packed FMA rate of the device in flop per second (FP32 or FP64)."""
-    p = _PRECS[prec] if isinstance(prec, str) else int(prec)
-    sink = torch.zeros(2, dtype=torch.float64, device=torch.cuda.current_device())
-    out = C.c_double(0.0)
-    L.check(L.load().dirac_probe_fma(p, _ptr(sink), C.byref(out), _stream()), "dirac_probe_fma")
-    return out.value
-
-
 def flops_per_site(op, nc: int) -> float:
     """App. E flop count per site and RHS of one apply."""
     return L.load().dirac_flops_per_site(_op(op), nc)

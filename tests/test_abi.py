@@ -159,7 +159,17 @@ def test_blas_and_misc_validation():
     assert lib.dirac_set_launch_shape(L.WILSON, L.FP32, 0, 0) == L.OK
     assert lib.dirac_set_launch_shape(L.WILSON, L.FP32, 1, 9) == L.EINVAL
     assert lib.dirac_set_launch_shape(L.WILSON, L.FP32, 0, 0) == L.OK
+
+
+def test_probe_library_exports_and_validation():
+    """The measurement library (include/dirac_probe.h) loads, exports its three calls, and rejects bad arguments
+    before any launch (host-side checks only: no device is touched)."""
+    from paper_2112_14640_amd import measure
+
+    lib = measure.load()
     out = C.c_double(0.0)
-    assert lib.dirac_probe_copy(FAKE_A, FAKE_B, 100, 1, C.byref(out), None) == L.EINVAL  # not a multiple of 16
-    assert lib.dirac_probe_copy(FAKE_A, FAKE_B, 1600, 0, C.byref(out), None) == L.EINVAL  # reps < 1
-    assert lib.dirac_probe_fma(L.BF16, FAKE_A, C.byref(out), None) == L.EINVAL
+    for name in ("dirac_probe_copy", "dirac_probe_fma", "dirac_probe_row_gather"):
+        assert hasattr(lib, name)
+    assert lib.dirac_probe_copy(None, None, 1600, 1, C.byref(out), None) == -1
+    assert lib.dirac_probe_fma(2, None, C.byref(out), None) == -1
+    assert lib.dirac_probe_row_gather(None, None, 4, 4, 4, 4, 48, 7, 1, C.byref(out), None) == -1

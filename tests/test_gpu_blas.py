@@ -87,14 +87,33 @@ def test_gamma5_and_epsilon():
 
 
 def test_measurement_probes():
-    """The copy and FMA probes return sane, finite rates and copy the data."""
+    """The copy, FMA and row-gather probes (their own library) return sane, finite rates; the copy copies, and the
+    row gather writes the exclusive or of each row and its six +-y, +-z, +-t neighbour rows."""
+    from paper_2112_14640_amd import measure
+
     src = torch.randn(2 ** 22, dtype=torch.float32, device="cuda:0")
     dst = torch.empty_like(src)
-    bw = dirac.probe_copy(src, dst, reps=3)
+    bw = measure.copy_rate(src, dst, reps=3)
     assert torch.equal(src, dst)
     assert 1e11 < bw < 2e13, bw
     for prec in ("fp32", "fp64"):
-        f = dirac.probe_fma(prec)
+        f = measure.fma_rate(prec)
         assert 1e12 < f < 4e14, (prec, f)
-    with pytest.raises(Exception):
-        dirac.probe_copy(src, dst[:-1])
+    with pytest.raises(ValueError):
+        measure.copy_rate(src, dst[:-1])
+    dims, site_bytes = (6, 4, 8, 6), 48
+    nx, ny, nz, nt = dims
+    a = torch.randint(0, 2 ** 31 - 1, (nt, nz, ny, nx, site_bytes // 4), dtype=torch.int32, device="cuda:0")
+    b = torch.empty_like(a)
+    r = measure.row_gather_rate(dims, site_bytes, a, b, reps=2)
+    assert 1e9 < r < 2e13, r
+    h = a.cpu()
+    want = h.clone()
+    for axis in (0, 1, 2):  # t, z, y
+        for s in (1, -1):
+            want ^= torch.roll(h, s, dims=axis)
+    assert torch.equal(b.cpu(), want)
+    measure.row_gather_rate(dims, site_bytes, a, b, reps=1, nrows=1)
+    assert torch.equal(b, a)
+    with pytest.raises(ValueError):
+        measure.row_gather_rate((6, 4, 6, 6), site_bytes, a, b)  # nz not a multiple of 4
