@@ -139,6 +139,21 @@ def test_brillouin_links_parity():
     assert np.max(np.abs(host(W32).astype(np.complex128) - ref32)) < 2e-6
 
 
+@pytest.mark.parametrize("nc", [1, 2, 3, 4])
+@pytest.mark.parametrize("dims", [(3, 3, 2, 3), (2, 4, 3, 2)])
+def test_brillouin_links_all_colours_and_ragged_tiles(nc, dims):
+    """The level-by-level link build against the oracle's path-by-path averages for every supported N_c, on
+    volumes that leave the last work-group's tile of sites partly empty (54 and 48 sites; tiles of 4 sites for
+    N_c <= 3, 2 for N_c = 4), with extents of 2 and 3 where the +1 and -1 steps reach the same neighbour."""
+    rng = np.random.default_rng(70 + nc)
+    U = si.gauge_field(rng, dims, nc, "haar")
+    ref = brillouin_links(U)
+    assert np.max(np.abs(host(dirac.brillouin_links(to_dev(U))) - ref)) < 1e-13
+    ref32 = brillouin_links(round_c64(U))
+    W32 = host(dirac.brillouin_links(to_dev(U, torch.complex64))).astype(np.complex128)
+    assert np.max(np.abs(W32 - ref32)) < 2e-6
+
+
 def test_brillouin_links_16x32_sampled():
     cfg = si.config("apply_16x32")
     rng = np.random.default_rng(cfg["seed"])
