@@ -408,17 +408,25 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
     u32x4 pre[PER];
     u32x4 hpre[2];
     G lpre[PERL];
+    // row copies and link windows are buffer loads over one lattice row: a scalar base per row, 32-bit
+    // offsets per lane (a read past the row returns zero instead of touching memory)
+    const uint32_t row_bytes = static_cast<uint32_t>(g.nx) * rt.units * 16u;
+    const uint32_t wrow_bytes = static_cast<uint32_t>(g.nx) * 40u * L * static_cast<uint32_t>(sizeof(G));
     auto fetch = [&](int rc) __attribute__((always_inline)) {
         const int64_t start = row_start(rc);
-        const u32x4* p = src + (start + x0) * rt.units + tt;
+        const auto rrow = raw_buffer(src + start * rt.units, row_bytes);
 #pragma unroll
-        for (int k = 0; k < PER; ++k) pre[k] = p[static_cast<int64_t>(k) * rt.threads];
+        for (int k = 0; k < PER; ++k)
+            pre[k] = buffer_load_unit<u32x4>(rrow, tt * 16u,
+                                             (static_cast<uint32_t>(x0) * rt.units + k * static_cast<uint32_t>(rt.threads)) *
+                                                 16u);
 #pragma unroll
         for (int q = 0; q < 2; ++q)
-            if (SEG && halo[q]) hpre[q] = src[start * rt.units + hsrc[q]];
+            if (SEG && halo[q]) hpre[q] = buffer_load_unit<u32x4>(rrow, hsrc[q] * 16u, 0u);
         const int dir0 = 9 * (3 * (rc / 9) + (rc / 3) % 3) + 3 * (rc % 3);
         const int64_t lstart = rc <= 13 ? own_start : start;
         const int wb = rc < 13 ? dir0 : (rc == 13 ? 37 : 78 - dir0);
+        const auto rw = raw_buffer(W + lstart * 40 * L, wrow_bytes);
 #pragma unroll
         for (int k = 0; k < PERL; ++k) {
             const uint32_t u = k * static_cast<uint32_t>(rt.threads) + tt;
@@ -426,7 +434,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
                 const uint32_t sx = u / LW;
                 const uint32_t e = u - sx * LW;
                 const int xs = SEG ? wrap(x0 - 1 + static_cast<int>(sx), g.nx) : static_cast<int>(sx);
-                lpre[k] = W[((lstart + xs) * 40 + wb) * L + e];
+                lpre[k] = buffer_load_unit<G>(rw, ((static_cast<uint32_t>(xs) * 40u + wb) * L + e) *
+                                                      static_cast<uint32_t>(sizeof(G)), 0u);
             }
         }
     };
