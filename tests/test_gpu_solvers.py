@@ -5,6 +5,7 @@ import torch
 
 import synthetic_inputs as si
 from oracle.brillouin import brillouin_apply, brillouin_apply_dagger, brillouin_links
+from oracle.clover import clover_apply, field_strength
 from oracle.solvers import cg as oracle_cg
 from oracle.staggered import staggered_apply, staggered_apply_dagger
 from oracle.wilson import wilson_apply, wilson_apply_dagger
@@ -126,3 +127,40 @@ def test_solver_edge_cases():
     bn[0, 0, 0, 0, 0, 0, 0] = np.nan
     with pytest.raises(RuntimeError, match="non-finite"):
         dirac.cg("wilson", Ud, to_dev(bn), MASS, tol=1e-10, maxit=10)
+
+
+# Shapes that take the row kernels (n_x * N_v / RB >= 64 threads per row), so that every CG step runs the fused
+# form: t = D p with per-row partial sums of |t|^2, then D^dagger t updating r in the epilogue (q never written).
+FUSED = {"wilson": (8, 4, 4, 8), "staggered": (16, 4, 4, 8)}
+
+
+@pytest.mark.parametrize("inner", [None, "fp32", "bf16"])
+@pytest.mark.parametrize("op,csw", [("wilson", 0.0), ("wilson", 1.0), ("staggered", 0.0)])
+def test_cg_fused_epilogue_path(op, csw, inner):
+    """CG on D^dagger D (Wilson also with the clover term, c_SW = 1) through the stencil epilogues, checked at
+    every site by the oracle's FP64 residual, and (plain FP64) step by step against the oracle's CG on the same
+    data."""
+    dims, nv = FUSED[op], 12
+    rng = np.random.default_rng(21)
+    U = si.gauge_field(rng, dims, NC, "near", 0.5)
+    b = si.staggered_vector(rng, dims, NC, nv) if op == "staggered" else si.wilson_vector(rng, dims, NC, nv)
+    Ud = to_dev(U)
+    kw = {} if inner is None else {"inner": inner, "gauge_lo": Ud.to(torch.complex64)}
+    a = _normal(op, U, MASS)
+    if csw:
+        F = field_strength(U)
+        kw["clover"] = dirac.clover_field(Ud, csw)
+        if inner is not None:
+            kw["clover_lo"] = dirac.clover_field(Ud.to(torch.complex64), csw)
+
+        def a(x):
+            y = wilson_apply(U, x, MASS) + clover_apply(F, x, csw)
+            return wilson_apply_dagger(U, y, MASS) + clover_apply(F, y, csw)
+    x, info = dirac.cg(op, Ud, to_dev(b), MASS, tol=1e-10, maxit=5000, history=inner is None, **kw)
+    assert info.reason == "converged", info
+    res = _colres(b - a(host(x)), b)
+    assert np.all(res < 1e-10), res
+    if inner is None:
+        ref = oracle_cg(a, b, tol=1e-12, maxit=4000)
+        for k in range(8):
+            np.testing.assert_allclose(info.alphas[k], ref.alphas[k], rtol=1e-9)
