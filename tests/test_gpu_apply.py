@@ -97,6 +97,23 @@ def test_small_lattice_parity(op, prec, case):
         parity(v, ref, TOL[prec], (op, prec, dims, nc, nv, dagger))
 
 
+# odd extents (the staggered phases need even ones) and an odd RHS count: (5,3,3,5) x 13 takes the row kernels
+# with 65 threads per row and one RHS per thread, (3,5,3,3) x 5 the direct kernels
+ODD = [((5, 3, 3, 5), 3, 13, True), ((3, 5, 3, 3), 2, 5, True), ((5, 3, 3, 5), 3, 13, False)]
+
+
+@pytest.mark.parametrize("op", ["wilson", "brillouin"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("case", range(len(ODD)))
+def test_odd_extents_and_rhs_parity(op, prec, case):
+    dims, nc, nv, apbc = ODD[case]
+    gauge, u = _inputs(op, dims, nc, nv, seed=140 + case)
+    for dagger in (False, True):
+        v, g_in, u_in = _run(op, prec, gauge, u, 0.07, apbc, dagger)
+        ref = ORACLE[(op, dagger)](g_in, u_in, 0.07, apbc)
+        parity(v, ref, TOL[prec], (op, prec, dims, nc, nv, dagger))
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("op", ["wilson", "staggered", "brillouin"])
 def test_apply_16x32_nv12_sampled(op, prec):
