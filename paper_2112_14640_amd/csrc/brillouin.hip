@@ -336,8 +336,8 @@ __global__ __launch_bounds__(256) void brillouin_kernel(const typename P::G* __r
 // flight (in registers) while the current one is consumed.  Three waves per SIMD cap the registers
 // at 168 (FP32 and BF16 fit, the segmented forms spill a few values); FP64, whose operands take
 // twice the registers, takes two waves per SIMD and up to 256.
-template <int NC, int RB, bool DAG, class P, int NVC, bool SEG>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(typename P::R) == 8 ? 2 : 3))) void brillouin_rows_kernel(const typename P::G* __restrict__ W,
+template <int NC, int RB, bool DAG, class P, int NVC, bool SEG, bool CS = false>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(typename P::R) == 8 && !CS ? 2 : 3))) void brillouin_rows_kernel(const typename P::G* __restrict__ W,
                                                              const typename P::S* __restrict__ in,
                                                              typename P::S* __restrict__ out, typename P::R diag,
                                                              Geom g, int nv, RowTile rt,
@@ -345,7 +345,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
     using R = typename P::R;
     using S = typename P::S;
     using G = typename P::G;
-    constexpr int PER = RowUnits<NC, RB, P>::PER;
+    // CS (colour split): a thread owns one colour row a of one RHS of its site (N_c threads per site and
+    // RHS), so its accumulators, link row and share of the row copy are a third as large
+    static_assert(!CS || RB == 1, "the colour-split form takes one RHS per thread");
+    constexpr int PER = CS ? RowUnits<NC, RB, P>::PER / NC : RowUnits<NC, RB, P>::PER;
+    constexpr int NA = CS ? 1 : NC;  // colour rows per thread
     constexpr int L = NC * NC;
     constexpr int LW = 3 * L;  // link-window elements per site
     extern __shared__ __align__(16) u32x4 rtile[];
@@ -361,7 +365,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
     const bool active = tid < static_cast<uint32_t>(rt.threads);
     const uint32_t tt = active ? tid : tid - rt.threads;  // padding threads shadow a real one
     const uint32_t j = fast_div(tt, rt.magic_nrg);      // site within the segment
-    const int rg = static_cast<int>(tt - j * rt.nrg);
+    const int rg = static_cast<int>(tt - j * rt.nrg);   // CS: ca * nv + rhs
+    const int ca = CS ? rg / nv : 0;                    // CS: the thread's colour row
+    const int col = CS ? rg - ca * nv : rg * RB;        // first RHS column of the thread
     const int x = x0 + static_cast<int>(j);
     int cy, cz, ct;
     {
@@ -379,7 +385,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
     const int SC = rt.S + 2 * OFF;    // sites per copy
     G* lwin = reinterpret_cast<G*>(rtile + SC * (rt.units + 1));  // SC * LW link elements
     const uint32_t nlink = static_cast<uint32_t>(SC) * LW;
-    constexpr int PERL = 4;  // link elements per thread (checked at launch)
+    constexpr int PERL = CS ? 2 : 4;  // link elements per thread (checked at launch)
     uint32_t slot[PER];      // main units: the S sites of the segment, copy sites 1 .. S
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
@@ -440,14 +446,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
         }
     };
     auto at = [&](int c) __attribute__((always_inline)) {
-        return reinterpret_cast<const S*>(rtile + c * (rt.units + 1)) + rg * RB;
+        return reinterpret_cast<const S*>(rtile + c * (rt.units + 1)) + col;
     };
 
-    cx<R> acc[RB][NC][4];
+    cx<R> acc[RB][NA][4];
 #pragma unroll
     for (int k = 0; k < RB; ++k)
 #pragma unroll
-        for (int a = 0; a < NC; ++a)
+        for (int a = 0; a < NA; ++a)
 #pragma unroll
             for (int s = 0; s < 4; ++s) acc[k][a][s] = {R(0), R(0)};
 
@@ -478,30 +484,57 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
 #pragma unroll
                     for (int k = 0; k < RB; ++k)
 #pragma unroll
-                        for (int a = 0; a < NC; ++a)
+                        for (int a = 0; a < NA; ++a)
 #pragma unroll
                             for (int s = 0; s < 4; ++s) {
-                                const cx<R> v = io<R, S>::ld(nbp + (a * 4 + s) * nv + k);
+                                const cx<R> v = io<R, S>::ld(nbp + ((CS ? ca : a) * 4 + s) * nv + k);
                                 acc[k][a][s].re += diag * v.re;
                                 acc[k][a][s].im += diag * v.im;
                             }
-                    if (clov) clover_add<NC, RB>(acc, nbp, nv, clov + (own_start + x) * clover_reals<NC>());
+                    if constexpr (!CS)  // the launcher takes the colour-split form only without a clover field
+                        if (clov) clover_add<NC, RB>(acc, nbp, nv, clov + (own_start + x) * clover_reals<NC>());
                     continue;
                 }
                 // W_d(n): stored at the own site (rc < 13, or rc = 13 with d_x = -1), else the
                 // adjoint of the stored link at n + d
                 // l holds the stored matrix; for the adjoint directions W_d(n) = l^+, applied below
                 // with conjugating multiply-adds instead of an explicit conjugate
-                cx<R> l[NC][NC];
+                // (CS: only the thread's row ca of W_d, i.e. row ca of l, or column ca for the adjoints)
+                cx<R> l[NA][NC];
                 const bool adj = rc > 13 || (rc == 13 && ix == 2);
                 const G* lp = lwin + (adj ? cn : static_cast<int>(j) + OFF) * LW +
                               (rc < 13 ? ix : (rc == 13 ? 2 : 2 - ix)) * L;
 #pragma unroll
-                for (int a = 0; a < NC; ++a)
+                for (int a = 0; a < NA; ++a)
 #pragma unroll
-                    for (int b = 0; b < NC; ++b) l[a][b] = io<R, G>::ld(lp + a * NC + b);
+                    for (int b = 0; b < NC; ++b) {
+                        if constexpr (CS)
+                            l[a][b] = io<R, G>::ld(lp + (adj ? b * NC + ca : ca * NC + b));
+                        else
+                            l[a][b] = io<R, G>::ld(lp + a * NC + b);
+                    }
                 const R* sv = spin_table<R>(DAG ? 1 : 0, flip, 27 * it + 9 * iz + 3 * iy + ix);
                 const R lh = sv[0], q1 = sv[1], q2 = sv[2], q3 = sv[3], q4 = sv[4];
+                if constexpr (CS) {
+                    // one colour row: the neighbour's colour components are consumed one at a time
+                    cx<R> ch[4] = {{R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}};
+#pragma unroll
+                    for (int b = 0; b < NC; ++b) {
+                        cx<R> pb[4];
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) pb[s] = io<R, S>::ld(nbp + (b * 4 + s) * nv);
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) {
+                            if (adj)
+                                cfma_conj(ch[s], l[0][b], pb[s]);
+                            else
+                                cfma(ch[s], l[0][b], pb[s]);
+                        }
+                    }
+                    spin_accumulate(acc[0][0], ch, lh, q1, q2, q3, q4, !lap && ix != 1, !lap && iy != 1,
+                                    !lap && iz != 1, !lap && it != 1);
+                    continue;
+                }
 #pragma unroll
                 for (int k = 0; k < RB; ++k) {
                     cx<R> p[NC][4];
@@ -510,13 +543,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
 #pragma unroll
                         for (int s = 0; s < 4; ++s) p[b][s] = io<R, S>::ld(nbp + (b * 4 + s) * nv + k);
 #pragma unroll
-                    for (int a = 0; a < NC; ++a) {
+                    for (int a = 0; a < NA; ++a) {
                         cx<R> ch[4] = {{R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}};
-                        if (adj) {  // (l^+)[a][b] = conj(l[b][a])
+                        if (adj) {  // (l^+)[a][b] = conj(l[b][a]); CS: l[0][b] already holds l[b][ca]
 #pragma unroll
                             for (int b = 0; b < NC; ++b)
 #pragma unroll
-                                for (int s = 0; s < 4; ++s) cfma_conj(ch[s], l[b][a], p[b][s]);
+                                for (int s = 0; s < 4; ++s) cfma_conj(ch[s], CS ? l[a][b] : l[b][a], p[b][s]);
                         } else {
 #pragma unroll
                             for (int b = 0; b < NC; ++b)
@@ -536,9 +569,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
 #pragma unroll
         for (int k = 0; k < RB; ++k)
 #pragma unroll
-            for (int a = 0; a < NC; ++a)
+            for (int a = 0; a < NA; ++a)
 #pragma unroll
-                for (int s = 0; s < 4; ++s) io<R, S>::st(o + (a * 4 + s) * nv + k, acc[k][a][s]);
+                for (int s = 0; s < 4; ++s) io<R, S>::st(o + ((CS ? ca : a) * 4 + s) * nv + k, acc[k][a][s]);
     }
     __syncthreads();
     u32x4* dst = reinterpret_cast<u32x4*>(out) + (own_start + x0) * rt.units;
@@ -587,14 +620,18 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
     const size_t block_bytes = static_cast<size_t>(NC) * 4 * a.nv * sizeof(S);
     if (block_bytes % 16 != 0 || !tile_aligned(a)) return false;
     const int units = static_cast<int>(block_bytes / 16);
-    const int nrg = a.nv / RB;
+    // FP64 takes the colour-split form (one colour row of one RHS per thread), which keeps its registers
+    // under the cap of three waves per SIMD; it carries no clover term (that case keeps the direct kernel)
+    constexpr bool kSplit = sizeof(typename P::R) == 8 && RB == 1;
+    if (kSplit && a.clover) return false;
+    const int nrg = kSplit ? a.nv * NC : a.nv / RB;
     const int64_t rows = a.g.vol / a.g.nx;
     // segment: the largest divisor of n_x with at most 256 threads (at most 512 if none), at least
     // 64 threads and enough threads for the two halo sites (two units each) and the link window
     auto fits = [&](int d, int cap) {
         const int64_t th = static_cast<int64_t>(d) * nrg;
         return a.g.nx % d == 0 && th <= cap && th >= 64 && units <= th &&
-               static_cast<int64_t>(d + 2) * 3 * NC * NC <= 4 * th;
+               static_cast<int64_t>(d + 2) * 3 * NC * NC <= (kSplit ? 2 : 4) * th;
     };
     int seg = 0;
     for (int cap : {256, 512}) {
@@ -637,7 +674,19 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
     };
     auto pick = [&](auto seg_c) {
         constexpr bool SG = decltype(seg_c)::value;
-        if (a.nv == 12 && RB == 1) {
+        if constexpr (kSplit) {
+            if (a.nv == 12) {
+                if (a.dagger)
+                    go(brillouin_rows_kernel<NC, RB, true, P, 12, SG, true>);
+                else
+                    go(brillouin_rows_kernel<NC, RB, false, P, 12, SG, true>);
+            } else {
+                if (a.dagger)
+                    go(brillouin_rows_kernel<NC, RB, true, P, 0, SG, true>);
+                else
+                    go(brillouin_rows_kernel<NC, RB, false, P, 0, SG, true>);
+            }
+        } else if (a.nv == 12 && RB == 1) {
             if (a.dagger)
                 go(brillouin_rows_kernel<NC, RB, true, P, 12, SG>);
             else
