@@ -192,6 +192,28 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
     if (threadIdx.x == 0) out[rhs * width_w + w] = sh[0];
 }
 
+// out[b * nv + rhs] = sum of partial[i * nv + rhs] over i in [b * chunk, min((b + 1) * chunk, nblk)).  Thread t
+// takes RHS t % nv and every (blockDim / nv)-th i of the range from t / nv on; lane 0 of each RHS then adds the
+// lanes' sums in order.  blockDim is a multiple of nv.
+constexpr int kRowSumBlocks = 256;
+__global__ __launch_bounds__(256) void k_sum_ranges(const double* __restrict__ partial, int64_t nblk, int nv,
+                                                    int64_t chunk, double* __restrict__ out) {
+    __shared__ double sh[256];
+    const int lanes = static_cast<int>(blockDim.x) / nv;
+    const int t = threadIdx.x, rhs = t % nv, lane = t / nv;
+    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * chunk;
+    const int64_t i1 = i0 + chunk < nblk ? i0 + chunk : nblk;
+    double s = 0.0;
+    for (int64_t i = i0 + lane; i < i1; i += lanes) s += partial[i * nv + rhs];
+    sh[t] = s;
+    __syncthreads();
+    if (lane == 0) {
+        double a = 0.0;
+        for (int l = 0; l < lanes; ++l) a += sh[l * nv + rhs];
+        out[static_cast<int64_t>(blockIdx.x) * nv + rhs] = a;
+    }
+}
+
 void finalize(const double* partial, int width_w, int nv, double* out, hipStream_t st) {
     hipLaunchKernelGGL(k_finalize, dim3(width_w * nv), dim3(256), 0, st, partial, static_cast<int64_t>(kReduceBlocks),
                        width_w, nv, out);
@@ -497,8 +519,14 @@ __global__ __launch_bounds__(256) void k_bicg_s(S* __restrict__ s, const S* __re
 
 }  // namespace
 
-void finalize_blocks(const double* partial, int64_t nblk, int nv, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_finalize, dim3(nv), dim3(256), 0, st, partial, nblk, 1, nv, out);
+void finalize_blocks(const double* partial, int64_t nblk, int nv, double* scratch, double* out, hipStream_t st) {
+    // stage 1: kRowSumBlocks blocks each add a contiguous range of blocks' partials for every RHS (coalesced
+    // reads); stage 2 adds the kRowSumBlocks results per RHS.  Both orders are fixed.
+    const int lanes = 256 / nv;
+    const int64_t chunk = (nblk + kRowSumBlocks - 1) / kRowSumBlocks;
+    hipLaunchKernelGGL(k_sum_ranges, dim3(kRowSumBlocks), dim3(lanes * nv), 0, st, partial, nblk, nv, chunk, scratch);
+    hipLaunchKernelGGL(k_finalize, dim3(nv), dim3(256), 0, st, scratch, static_cast<int64_t>(kRowSumBlocks), 1, nv,
+                       out);
 }
 
 int blas_norm2(dirac_prec p, const void* x, int64_t nrows, int nv, double* partial, double* out, hipStream_t st) {

@@ -82,8 +82,8 @@ inline size_t reduce_partial_doubles(int nv) { return static_cast<size_t>(kReduc
 
 int blas_norm2(dirac_prec p, const void* x, int64_t nrows, int nv, double* partial, double* out, hipStream_t st);
 // out[rhs] = sum over nblk blocks of partial[b * nv + rhs] (fixed order), e.g. the per-tile partials
-// of a stencil epilogue
-void finalize_blocks(const double* partial, int64_t nblk, int nv, double* out, hipStream_t st);
+// of a stencil epilogue; scratch: 256 * nv doubles of device memory
+void finalize_blocks(const double* partial, int64_t nblk, int nv, double* scratch, double* out, hipStream_t st);
 // Device address of the library's own reduction partials on the current device (found once per
 // device); static_scratch_doubles() doubles, enough for reduce_partial_doubles(256).
 int static_scratch(double** out);

@@ -238,7 +238,7 @@ int fused_normal_step(const OpCtx& o, dirac_prec pp, const Field& f, const void*
     e1.partial = s.tiles;
     int rc = apply_op(o, pp, f, p, t, false, st, e1);
     if (rc) return rc;
-    finalize_blocks(s.tiles, s.ntiles, o.nv, s.pq, st);
+    finalize_blocks(s.tiles, s.ntiles, o.nv, s.partial, s.pq, st);
     alpha_kernel();
     Epilogue e2;
     e2.mode = 2;
@@ -246,7 +246,7 @@ int fused_normal_step(const OpCtx& o, dirac_prec pp, const Field& f, const void*
     e2.r = r;
     e2.alpha = s.alpha;
     if ((rc = apply_op(o, pp, f, t, q, true, st, e2))) return rc;
-    finalize_blocks(s.tiles, s.ntiles, o.nv, s.rr_new, st);
+    finalize_blocks(s.tiles, s.ntiles, o.nv, s.partial, s.rr_new, st);
     return DIRAC_OK;
 }
 
