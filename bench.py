@@ -379,8 +379,13 @@ def run_cg(torch, dirac, si):
                                                           if "max_rel_error_vs_fp64" in r else ""))
         return x, info, r
 
+    # untimed warm-up of every path (first-call costs: staging buffers, code objects)
+    for inner in (None, "fp32", "bf16"):
+        dirac.cg("wilson", U, b, m, tol=1e-10, maxit=3, inner=inner, gauge_lo=U32 if inner else None)
+    torch.cuda.synchronize()
     x64, _, out["fp64"] = solve("fp64", None, {})
     runs = [("mixed_fp32", "fp32", {}), ("mixed_bf16", "bf16", {}),
+            ("mixed_fp32_delta_0.01", "fp32", {"delta": 0.01}), ("mixed_bf16_delta_0.01", "bf16", {"delta": 0.01}),
             ("mixed_fp32_defect_correction", "fp32", {"mixed_scheme": 1}),
             ("mixed_bf16_defect_correction", "bf16", {"mixed_scheme": 1})]
     for name, inner, opts in runs:
