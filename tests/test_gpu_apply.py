@@ -114,6 +114,21 @@ def test_odd_extents_and_rhs_parity(op, prec, case):
         parity(v, ref, TOL[prec], (op, prec, dims, nc, nv, dagger))
 
 
+@pytest.mark.parametrize("op", ["wilson", "staggered", "brillouin"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_largest_rhs_count(op, prec):
+    """N_v = 256, the largest the library takes (Wilson and staggered rows of 512 and 256 threads, Brillouin on
+    the direct kernel), and N_v = 257 refused before any launch."""
+    dims, nc, nv = (2, 2, 2, 4), 3, 256
+    gauge, u = _inputs(op, dims, nc, nv, seed=150)
+    for dagger in (False, True):
+        v, g_in, u_in = _run(op, prec, gauge, u, 0.07, True, dagger)
+        parity(v, ORACLE[(op, dagger)](g_in, u_in, 0.07, True), TOL[prec], (op, prec, nv, dagger))
+    _, u_big = _inputs(op, dims, nc, nv + 1, seed=151)
+    with pytest.raises(Exception):
+        _run(op, prec, gauge, u_big, 0.07, True, False)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("op", ["wilson", "staggered", "brillouin"])
 def test_apply_16x32_nv12_sampled(op, prec):
