@@ -260,9 +260,12 @@ __global__ __launch_bounds__(kReduceThreads) void k_dot(const SX* __restrict__ x
 }
 
 // Elementwise kernels: grid-stride over complex elements, rhs = element % nv.
+// Grid of an element-wise kernel: one element (or pack) per thread.  The kernels are grid-stride loops,
+// so a capped grid is still correct; a grid covering every element measured 10-13 % faster than one of
+// 8192 work-groups looping over it (FP32 x/p update at 32^3 x 64: 2.19 against 2.51 ms).
 inline dim3 ew_grid(int64_t n) {
     int64_t b = (n + 255) / 256;
-    if (b > 256 * 32) b = 256 * 32;
+    if (b > (int64_t{1} << 30)) b = int64_t{1} << 30;
     if (b < 1) b = 1;
     return dim3(static_cast<unsigned>(b));
 }
