@@ -459,6 +459,69 @@ __global__ __launch_bounds__(kReduceThreads) void k_xp_update_dot(SX* __restrict
     block_partials_packed<2, VW>(acc, pl, partial);
 }
 
+// The same update with kBurstRows rows per thread, taken once with every load issued before any
+// arithmetic (element-wise kernels whose threads loop over many rows measured 10-13 % slower); one
+// partial per block, kBurstRows * rows-per-block rows per block.
+constexpr int kBurstRows = 4;
+template <int VW, typename SX, typename SP, typename SR>
+__global__ __launch_bounds__(kReduceThreads) void k_xp_update_dot_burst(SX* __restrict__ x, SP* __restrict__ p,
+                                                                         const SR* __restrict__ r,
+                                                                         const double2* __restrict__ alpha,
+                                                                         const double2* __restrict__ beta,
+                                                                         int64_t nrows, int nv,
+                                                                         double* __restrict__ partial) {
+    const PackLane pl = pack_lane(nv / VW);
+    double acc[2][VW] = {};
+    if (pl.roff < pl.rpb) {
+        cx<double> al[VW], be[VW];
+#pragma unroll
+        for (int i = 0; i < VW; ++i) {
+            const double2 a = alpha[pl.pk * VW + i], b = beta[pl.pk * VW + i];
+            al[i] = {a.x, a.y};
+            be[i] = {b.x, b.y};
+        }
+        const int64_t row0 = static_cast<int64_t>(blockIdx.x) * (kBurstRows * pl.rpb) + pl.roff;
+        cx<double> pv[kBurstRows][VW], xv[kBurstRows][VW], rv[kBurstRows][VW];
+#pragma unroll
+        for (int q = 0; q < kBurstRows; ++q) {
+            const int64_t row = row0 + static_cast<int64_t>(q) * pl.rpb;
+            if (row < nrows) {
+                const int64_t e = row * nv + pl.pk * VW;
+                ldp<VW>(p + e, pv[q]);
+                ldp<VW>(x + e, xv[q]);
+                ldp<VW>(r + e, rv[q]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kBurstRows; ++q) {
+            const int64_t row = row0 + static_cast<int64_t>(q) * pl.rpb;
+            if (row >= nrows) continue;
+            const int64_t e = row * nv + pl.pk * VW;
+            cx<double> np[VW];
+#pragma unroll
+            for (int i = 0; i < VW; ++i) {
+                cfma(xv[q][i], al[i], pv[q][i]);
+                np[i] = rv[q][i];
+                cfma(np[i], be[i], pv[q][i]);
+            }
+            stp<VW>(x + e, xv[q]);
+            stp<VW>(p + e, np);
+#pragma unroll
+            for (int i = 0; i < VW; ++i) {
+                const cx<double> ps = stored_value<SP>(np[i]);  // <r, p> of p as stored
+                acc[0][i] += rv[q][i].re * ps.re + rv[q][i].im * ps.im;
+                acc[1][i] += rv[q][i].re * ps.im - rv[q][i].im * ps.re;
+            }
+        }
+    }
+    block_partials_packed<2, VW>(acc, pl, partial);
+}
+
+inline int64_t burst_blocks(int64_t nrows, int nv, int vw) {
+    const int64_t rows_per_block = static_cast<int64_t>(kBurstRows) * (kReduceThreads / (nv / vw));
+    return (nrows + rows_per_block - 1) / rows_per_block;
+}
+
 // BiCGstab: x += alpha p + omega s ; r = s - omega t ; partial ||r||^2
 template <typename S>
 __global__ __launch_bounds__(kReduceThreads) void k_bicg_xr(S* __restrict__ x, const S* __restrict__ p,
@@ -717,9 +780,15 @@ int fused_xp_update(dirac_prec px, void* x, dirac_prec pp, void* p, dirac_prec p
     });
 }
 
+size_t burst_partial_doubles(int64_t nrows, int nv) {
+    // the largest block count is that of single-column packs; 2 nv columns must fit one row-sum block
+    if (nv < 1 || 2 * nv > 256) return 0;
+    return static_cast<size_t>(burst_blocks(nrows, nv, 1)) * 2 * nv;
+}
+
 int fused_xp_update_dot(dirac_prec px, void* x, dirac_prec pp, void* p, dirac_prec prr, const void* r,
                         const double* alpha, const double* beta, int64_t nrows, int nv, double* partial, double* rp,
-                        hipStream_t st) {
+                        hipStream_t st, double* burst, size_t burst_doubles) {
     return with_prec(px, [&](auto tx) {
         return with_prec(pp, [&](auto tp) {
             return with_prec(prr, [&](auto trr) {
@@ -727,7 +796,29 @@ int fused_xp_update_dot(dirac_prec px, void* x, dirac_prec pp, void* p, dirac_pr
                 using SP = typename decltype(tp)::type;
                 using SR = typename decltype(trr)::type;
                 constexpr int VW = pack_width<SX, SP, SR>();
-                if (pack_ok(VW, nv, {x, p, r}))
+                const int vw = pack_ok(VW, nv, {x, p, r}) ? VW : 1;
+                const int64_t nb = burst_blocks(nrows, nv, vw);
+                if (burst && 2 * nv <= 256 && static_cast<size_t>(nb) * 2 * nv <= burst_doubles) {
+                    if (vw == VW)
+                        hipLaunchKernelGGL((k_xp_update_dot_burst<VW, SX, SP, SR>), dim3(static_cast<unsigned>(nb)),
+                                           dim3(kReduceThreads), 0, st, static_cast<SX*>(x), static_cast<SP*>(p),
+                                           static_cast<const SR*>(r), reinterpret_cast<const double2*>(alpha),
+                                           reinterpret_cast<const double2*>(beta), nrows, nv, burst);
+                    else
+                        hipLaunchKernelGGL((k_xp_update_dot_burst<1, SX, SP, SR>), dim3(static_cast<unsigned>(nb)),
+                                           dim3(kReduceThreads), 0, st, static_cast<SX*>(x), static_cast<SP*>(p),
+                                           static_cast<const SR*>(r), reinterpret_cast<const double2*>(alpha),
+                                           reinterpret_cast<const double2*>(beta), nrows, nv, burst);
+                    // the partials are [block][w][rhs]: rows of 2 nv columns summed in ranges, then per (rhs, w)
+                    const int lanes = 256 / (2 * nv);
+                    const int64_t chunk = (nb + kRowSumBlocks - 1) / kRowSumBlocks;
+                    hipLaunchKernelGGL(k_sum_ranges, dim3(kRowSumBlocks), dim3(lanes * 2 * nv), 0, st, burst, nb, 2 * nv,
+                                       chunk, partial);
+                    hipLaunchKernelGGL(k_finalize, dim3(2 * nv), dim3(256), 0, st, partial,
+                                       static_cast<int64_t>(kRowSumBlocks), 2, nv, rp);
+                    return DIRAC_OK;
+                }
+                if (vw == VW)
                     hipLaunchKernelGGL((k_xp_update_dot<VW, SX, SP, SR>), dim3(kReduceBlocks), dim3(kReduceThreads), 0,
                                        st, static_cast<SX*>(x), static_cast<SP*>(p), static_cast<const SR*>(r),
                                        reinterpret_cast<const double2*>(alpha), reinterpret_cast<const double2*>(beta),

@@ -109,10 +109,13 @@ int fused_r_update(dirac_prec pr, void* r, dirac_prec pq, const void* q, const d
 // x += alpha p ; p = r + beta p   (x precision px; r, p precision pp)
 int fused_xp_update(dirac_prec px, void* x, dirac_prec pp, void* p, dirac_prec prr, const void* r, const double* alpha,
                     const double* beta, int64_t nrows, int nv, hipStream_t st);
-// x += alpha p ; p = r + beta p ; rp = <r, p> of the new p as stored (2 nv doubles, re/im per RHS)
+// x += alpha p ; p = r + beta p ; rp = <r, p> of the new p as stored (2 nv doubles, re/im per RHS).
+// With `burst` (device, burst_partial_doubles(nrows, nv) doubles, may be null) each thread takes a few
+// rows once, all loads first, and the per-block partials are summed in two fixed-order stages.
+size_t burst_partial_doubles(int64_t nrows, int nv);
 int fused_xp_update_dot(dirac_prec px, void* x, dirac_prec pp, void* p, dirac_prec prr, const void* r,
                         const double* alpha, const double* beta, int64_t nrows, int nv, double* partial, double* rp,
-                        hipStream_t st);
+                        hipStream_t st, double* burst = nullptr, size_t burst_doubles = 0);
 // y = b - y  (residual from A x stored in y)
 int blas_bminus(dirac_prec pb, const void* b, dirac_prec py, void* y, int64_t nrows, int nv, hipStream_t st);
 // r = b - q (all complex elements, any precisions)

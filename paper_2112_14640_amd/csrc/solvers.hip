@@ -132,11 +132,15 @@ struct Scalars {
     double* rp = nullptr;       // 2nv: <r, p> (reliable-update line search)
     double* tiles = nullptr;    // ntiles * nv: per-tile partial sums of the stencil epilogues
     int64_t ntiles = 0;
+    double* burst = nullptr;    // per-block partials of the one-pass x/p update with <r, p>
+    size_t burst_doubles = 0;
     double* hbuf = nullptr;     // pinned host, 16 nv doubles
-    void carve(Carver& c, int nv_, int64_t ntiles_) {
+    void carve(Carver& c, int nv_, int64_t ntiles_, int64_t nrows) {
         nv = nv_;
         ntiles = ntiles_;
         tiles = static_cast<double*>(c.take(static_cast<size_t>(ntiles) * nv * sizeof(double)));
+        burst_doubles = burst_partial_doubles(nrows, nv);
+        burst = static_cast<double*>(c.take(burst_doubles * sizeof(double)));
         partial = static_cast<double*>(c.take(reduce_partial_doubles(nv) * sizeof(double)));
         rr = static_cast<double*>(c.take(nv * sizeof(double)));
         rr_new = static_cast<double*>(c.take(nv * sizeof(double)));
@@ -492,7 +496,7 @@ int cg_reliable(const OpCtx& o, const RUVecs& v, const Rules& ru, double delta, 
         update = update || suggest;
         hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, st, s.rr_new, s.rr, s.mask, s.beta, nv);
         if ((rc = fused_xp_update_dot(F32, v.xl, v.pin, v.p, F32, v.r, s.alpha, s.beta, o.nrows, nv, s.partial, s.rp,
-                                      st)))
+                                      st, s.burst, s.burst_doubles)))
             return rc;
         if (!update) continue;
         // x += xl in FP64, true residual, replace the inner residual (keep p)
@@ -891,7 +895,7 @@ size_t solver_workspace_bytes(dirac_op op, int solver, dirac_prec outer, dirac_p
     Layout l = layout_for(solver, outer, inner, scheme);
     Carver c{nullptr, 0};
     Scalars s;
-    s.carve(c, nv, g.vol / g.nx);
+    s.carve(c, nv, g.vol / g.nx, o.nrows);
     for (int i = 0; i < l.n_out; ++i) c.take(vec_bytes(o, outer));
     for (int i = 0; i < l.n_hi; ++i) c.take(vec_bytes(o, DIRAC_FP64));
     for (int i = 0; i < l.n_f32; ++i) c.take(vec_bytes(o, DIRAC_FP32));
@@ -915,7 +919,7 @@ int run_solver(int solver, dirac_op op, dirac_prec outer, dirac_prec inner, cons
     if (mis) base += kAlign - mis;
     Carver c{base, ws_bytes};
     Scalars s;
-    s.carve(c, nv, g.vol / g.nx);
+    s.carve(c, nv, g.vol / g.nx, o.nrows);
     const bool mixed = inner != outer;
     Rules ru;
     ru.tol = tol;
