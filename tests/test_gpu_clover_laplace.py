@@ -101,9 +101,11 @@ def test_clover_apply_small(case, op, prec, variant):
         dirac.set_launch_shape(op, prec, 0, 0)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("op", ["wilson", "brillouin"])
-def test_clover_apply_16x32_sampled(op):
-    """16^3x32, Nc=3, Nv=12, FP32, links exp(i 0.3 H), m=0.05, c_SW=1 at ~1000 sampled sites."""
+def test_clover_apply_16x32_sampled(op, prec):
+    """16^3x32, Nc=3, Nv=12, FP32 or BF16 vectors (FP32 links and clover field), links exp(i 0.3 H), m=0.05,
+    c_SW=1 at ~1000 sampled sites."""
     cfg = si.config("apply_16x32")
     rng = np.random.default_rng(cfg["seed"])
     dims, nc, nv, m = cfg["dims"], cfg["nc"], cfg["nv"], cfg["mass"]
@@ -112,7 +114,8 @@ def test_clover_apply_16x32_sampled(op):
     U32 = to_dev(U, torch.complex64)
     C = dirac.clover_field(U32, 1.0)
     sites = sample_sites(dims, 1000)
-    Uo, u_in = round_c64(U), round_c64(u)
+    Uo = round_c64(U)
+    ud, u_in = _vec(u, prec)
     F = field_strength(Uo)
     if op == "brillouin":
         from oracle.brillouin import brillouin_apply_sites, brillouin_links_all
@@ -121,16 +124,15 @@ def test_clover_apply_16x32_sampled(op):
         W81 = brillouin_links_all(Uo, sites=sites)
     else:
         gauge = U32
-    ud = to_dev(u, torch.complex64)
     for dagger in (False, True):
         fn = dirac.apply_dagger if dagger else dirac.apply
-        v = at_sites(host(fn(op, gauge, ud, m, clover=C)).astype(np.complex128), sites)
+        v = at_sites(_host(fn(op, gauge, ud, m, clover=C), prec), sites)
         if op == "brillouin":
             ref = brillouin_apply_sites(W81, u_in, m, sites, True, dagger)
         else:
             ref = DIRAC[(op, dagger)](Uo, u_in, m, True, sites=sites)
         ref = ref + clover_apply(F, u_in, 1.0, sites=sites)
-        parity(v, ref, 1e-5, (op, dagger))
+        parity(v, ref, TOL[prec], (op, prec, dagger))
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
@@ -165,7 +167,8 @@ def test_laplace_apply_small(case, op, prec):
 
 
 @pytest.mark.parametrize("op", ["wilson_laplace", "brillouin_laplace"])
-def test_laplace_16x32_sampled(op):
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_laplace_16x32_sampled(op, prec):
     cfg = si.config("apply_16x32")
     rng = np.random.default_rng(cfg["seed"] + 1)
     dims, nc, nv, m = cfg["dims"], cfg["nc"], cfg["nv"], cfg["mass"]
@@ -173,14 +176,15 @@ def test_laplace_16x32_sampled(op):
     u = si.wilson_vector(rng, dims, nc, nv)
     U32 = to_dev(U, torch.complex64)
     sites = sample_sites(dims, 600)
-    Uo, u_in = round_c64(U), round_c64(u)
-    v = at_sites(host(dirac.apply(op, dirac.brillouin_links(U32) if op == "brillouin_laplace" else U32,
-                                  to_dev(u, torch.complex64), m)).astype(np.complex128), sites)
+    Uo = round_c64(U)
+    ud, u_in = _vec(u, prec)
+    v = at_sites(_host(dirac.apply(op, dirac.brillouin_links(U32) if op == "brillouin_laplace" else U32, ud, m),
+                       prec), sites)
     if op == "brillouin_laplace":
         ref = LAPLACE[op](brillouin_links(Uo), u_in, m, True, sites=sites)
     else:
         ref = LAPLACE[op](Uo, u_in, m, True, sites=sites)
-    parity(v, ref, 1e-5, op)
+    parity(v, ref, TOL[prec], (op, prec))
 
 
 def _colres(r, b):
