@@ -130,7 +130,6 @@ int choose_rb(dirac_op op, dirac_prec prec, int nc, int nv, const Geom& g) {
 int choose_variant(dirac_op op, dirac_prec prec) {
     const int o = g_variant_override[op][prec];
     if (o > 0) return o;
-    if (op_uses_w(op)) return prec == DIRAC_FP64 ? 1 : 4;
     return 4;
 }
 

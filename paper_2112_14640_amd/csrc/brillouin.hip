@@ -197,6 +197,36 @@ __global__ __launch_bounds__(kLinkThreads) void links_kernel(const GI* __restric
 //   g_3: rows <- (-i 2, +i 3, +i 0, -i 1)
 //   g_2: rows <- (-3, +2, +1, -0)
 //   g_1: rows <- (-i 3, -i 2, +i 1, +i 0)
+// gamma_<mu>_accumulate: one term alone, o[s] += q (g_mu ch)[s].
+template <typename R>
+__device__ __forceinline__ void gamma_x_accumulate(cx<R> (&o)[4], const cx<R> (&ch)[4], R q1) {
+    o[0].re += q1 * ch[3].im; o[0].im -= q1 * ch[3].re;
+    o[1].re += q1 * ch[2].im; o[1].im -= q1 * ch[2].re;
+    o[2].re -= q1 * ch[1].im; o[2].im += q1 * ch[1].re;
+    o[3].re -= q1 * ch[0].im; o[3].im += q1 * ch[0].re;
+}
+template <typename R>
+__device__ __forceinline__ void gamma_y_accumulate(cx<R> (&o)[4], const cx<R> (&ch)[4], R q2) {
+    o[0].re -= q2 * ch[3].re; o[0].im -= q2 * ch[3].im;
+    o[1].re += q2 * ch[2].re; o[1].im += q2 * ch[2].im;
+    o[2].re += q2 * ch[1].re; o[2].im += q2 * ch[1].im;
+    o[3].re -= q2 * ch[0].re; o[3].im -= q2 * ch[0].im;
+}
+template <typename R>
+__device__ __forceinline__ void gamma_z_accumulate(cx<R> (&o)[4], const cx<R> (&ch)[4], R q3) {
+    o[0].re += q3 * ch[2].im; o[0].im -= q3 * ch[2].re;
+    o[1].re -= q3 * ch[3].im; o[1].im += q3 * ch[3].re;
+    o[2].re -= q3 * ch[0].im; o[2].im += q3 * ch[0].re;
+    o[3].re += q3 * ch[1].im; o[3].im -= q3 * ch[1].re;
+}
+template <typename R>
+__device__ __forceinline__ void gamma_t_accumulate(cx<R> (&o)[4], const cx<R> (&ch)[4], R q4) {
+    o[0].re += q4 * ch[2].re; o[0].im += q4 * ch[2].im;
+    o[1].re += q4 * ch[3].re; o[1].im += q4 * ch[3].im;
+    o[2].re += q4 * ch[0].re; o[2].im += q4 * ch[0].im;
+    o[3].re += q4 * ch[1].re; o[3].im += q4 * ch[1].im;
+}
+
 template <typename R>
 __device__ __forceinline__ void spin_accumulate(cx<R> (&o)[4], const cx<R> (&ch)[4], R lh, R q1, R q2, R q3, R q4,
                                                 bool hx, bool hy, bool hz, bool ht) {
@@ -205,30 +235,10 @@ __device__ __forceinline__ void spin_accumulate(cx<R> (&o)[4], const cx<R> (&ch)
         o[s].re -= lh * ch[s].re;
         o[s].im -= lh * ch[s].im;
     }
-    if (ht) {
-        o[0].re += q4 * ch[2].re; o[0].im += q4 * ch[2].im;
-        o[1].re += q4 * ch[3].re; o[1].im += q4 * ch[3].im;
-        o[2].re += q4 * ch[0].re; o[2].im += q4 * ch[0].im;
-        o[3].re += q4 * ch[1].re; o[3].im += q4 * ch[1].im;
-    }
-    if (hz) {
-        o[0].re += q3 * ch[2].im; o[0].im -= q3 * ch[2].re;
-        o[1].re -= q3 * ch[3].im; o[1].im += q3 * ch[3].re;
-        o[2].re -= q3 * ch[0].im; o[2].im += q3 * ch[0].re;
-        o[3].re += q3 * ch[1].im; o[3].im -= q3 * ch[1].re;
-    }
-    if (hy) {
-        o[0].re -= q2 * ch[3].re; o[0].im -= q2 * ch[3].im;
-        o[1].re += q2 * ch[2].re; o[1].im += q2 * ch[2].im;
-        o[2].re += q2 * ch[1].re; o[2].im += q2 * ch[1].im;
-        o[3].re -= q2 * ch[0].re; o[3].im -= q2 * ch[0].im;
-    }
-    if (hx) {
-        o[0].re += q1 * ch[3].im; o[0].im -= q1 * ch[3].re;
-        o[1].re += q1 * ch[2].im; o[1].im -= q1 * ch[2].re;
-        o[2].re -= q1 * ch[1].im; o[2].im += q1 * ch[1].re;
-        o[3].re -= q1 * ch[0].im; o[3].im += q1 * ch[0].re;
-    }
+    if (ht) gamma_t_accumulate(o, ch, q4);
+    if (hz) gamma_z_accumulate(o, ch, q3);
+    if (hy) gamma_y_accumulate(o, ch, q2);
+    if (hx) gamma_x_accumulate(o, ch, q1);
 }
 
 template <int NC, int RB, bool DAG, class P>
@@ -332,10 +342,14 @@ __global__ __launch_bounds__(256) void brillouin_kernel(const typename P::G* __r
 // site of one row: for rc < 13 the directions dir0 .. dir0 + 2 (dir0 = 27 it + 9 iz + 3 iy) of the
 // own row; for rc > 13 the directions 78 - dir0 .. 80 - dir0 of the neighbour row, whose adjoints
 // are the links of the directions 80 - dir (Tab. off-axis); for rc = 13 direction 39 of the own
-// row serves d_x = -1 as stored and d_x = +1 as the adjoint at x + 1.  The next row copy is in
-// flight (in registers) while the current one is consumed.  Three waves per SIMD cap the registers
-// at 168 (FP32 and BF16 fit, the segmented forms spill a few values); FP64, whose operands take
-// twice the registers, takes two waves per SIMD and up to 256.
+// row serves d_x = -1 as stored and d_x = +1 as the adjoint at x + 1.  The window holds each link as
+// applied: adjoints transposed and conjugated, and the fermion sign of a t step across the boundary
+// folded in, so that every hop is the same plain product.  The next row copy is in flight (in
+// registers) while the current one is consumed.  Per row, the hop d_x = 0 is applied on its own, and
+// the hops d_x = -1 and +1, whose spin factors differ only in the sign of the gamma_x term, share one
+// accumulator (a third fewer spin-factor multiply-adds than one hop at a time).  Three waves per SIMD
+// cap the registers at 168 (FP32 and BF16 fit, the segmented forms spill a few values); FP64, whose
+// operands take twice the registers, takes the colour-split form (CS) at three waves per SIMD.
 template <int NC, int RB, bool DAG, class P, int NVC, bool SEG, bool CS = false>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(typename P::R) == 8 && !CS ? 2 : 3))) void brillouin_rows_kernel(const typename P::G* __restrict__ W,
                                                              const typename P::S* __restrict__ in,
@@ -347,7 +361,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
     using G = typename P::G;
     // CS (colour split): a thread owns one colour row a of one RHS of its site (N_c threads per site and
     // RHS), so its accumulators, link row and share of the row copy are a third as large
-    static_assert(!CS || RB == 1, "the colour-split form takes one RHS per thread");
+    static_assert(RB == 1, "the row form takes one RHS per thread");
     constexpr int PER = CS ? RowUnits<NC, RB, P>::PER / NC : RowUnits<NC, RB, P>::PER;
     constexpr int NA = CS ? 1 : NC;  // colour rows per thread
     constexpr int L = NC * NC;
@@ -414,6 +428,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
     u32x4 pre[PER];
     u32x4 hpre[2];
     G lpre[PERL];
+    uint32_t lneg = 0;  // bits 2k, 2k + 1: negate the real, imaginary part of lpre[k] when it is stored
     // row copies and link windows are buffer loads over one lattice row: a scalar base per row, 32-bit
     // offsets per lane (a read past the row returns zero instead of touching memory)
     const uint32_t row_bytes = static_cast<uint32_t>(g.nx) * rt.units * 16u;
@@ -433,15 +448,30 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
         const int64_t lstart = rc <= 13 ? own_start : start;
         const int wb = rc < 13 ? dir0 : (rc == 13 ? 37 : 78 - dir0);
         const auto rw = raw_buffer(W + lstart * 40 * L, wrow_bytes);
+        // the fermion sign of a t step across the boundary rides on the row's links (all three hops of a
+        // row copy take the same t step)
+        const int itf = rc / 9;
+        const bool bflip = g.apbc && ((itf == 0 && ct == 0) || (itf == 2 && ct == g.nt - 1));
+        lneg = 0;
 #pragma unroll
         for (int k = 0; k < PERL; ++k) {
-            const uint32_t u = k * static_cast<uint32_t>(rt.threads) + tt;
-            if (u < nlink) {
+            // every lane loads (lanes past the window repeat its last element, which they do not store):
+            // a conditional load would be copied out of its register and waited for here
+            const uint32_t u = min(k * static_cast<uint32_t>(rt.threads) + tt, nlink - 1u);
+            {
                 const uint32_t sx = u / LW;
                 const uint32_t e = u - sx * LW;
+                const uint32_t slot = e / L, ab = e - slot * L;
+                // window slot `slot` holds W_d(n) as applied: for rc > 13 every slot is the adjoint of the
+                // stored link (element (a, b) <- conj of stored (b, a)); for rc = 13 slot 2 holds direction
+                // 39 as stored and slot 0 its adjoint
+                const bool adj = rc > 13 || (rc == 13 && slot == 0);
+                const uint32_t from = (rc == 13 && slot == 0 ? 2u : slot) * L +
+                                      (adj ? (ab % NC) * NC + ab / NC : ab);
                 const int xs = SEG ? wrap(x0 - 1 + static_cast<int>(sx), g.nx) : static_cast<int>(sx);
-                lpre[k] = buffer_load_unit<G>(rw, ((static_cast<uint32_t>(xs) * 40u + wb) * L + e) *
+                lpre[k] = buffer_load_unit<G>(rw, ((static_cast<uint32_t>(xs) * 40u + wb) * L + from) *
                                                       static_cast<uint32_t>(sizeof(G)), 0u);
+                lneg |= (bflip ? 1u << (2 * k) : 0u) | (adj != bflip ? 2u << (2 * k) : 0u);
             }
         }
     };
@@ -465,102 +495,95 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
 #pragma unroll
         for (int q = 0; q < 2; ++q)
             if (SEG && halo[q]) rtile[hslot[q]] = hpre[q];
+        // the sign changes stay here, after the barrier: taken at the loads, they would wait for the
+        // prefetch there and serialise it with the row's arithmetic
+        uint32_t negm = lneg;
+        asm volatile("" : "+v"(negm));
 #pragma unroll
         for (int k = 0; k < PERL; ++k) {
             const uint32_t u = k * static_cast<uint32_t>(rt.threads) + tt;
-            if (u < nlink) lwin[u] = lpre[k];
+            if (u < nlink) {
+                G v = lpre[k];
+                if (negm & (1u << (2 * k))) v.x = -v.x;
+                if (negm & (2u << (2 * k))) v.y = -v.y;
+                lwin[u] = v;
+            }
         }
         __syncthreads();
-        if (rc < 26) fetch(rc + 1);
+        // the last pass refetches its own row (a cache hit): an unconditional fetch keeps the prefetched
+        // values in the registers they are loaded into
+        fetch(rc < 26 ? rc + 1 : 26);
         if (active) {
             const int iy = rc % 3, iz = (rc / 3) % 3, it = rc / 9;
-            const int flip = (g.apbc && ((it == 0 && ct == 0) || (it == 2 && ct == g.nt - 1))) ? 1 : 0;
-#pragma unroll
-            for (int ix = 0; ix < 3; ++ix) {
-                // copy site of x + ix - 1
+            const int dir0 = 27 * it + 9 * iz + 3 * iy;  // + ix for d_x = ix - 1
+            const bool hy = !lap && iy != 1, hz = !lap && iz != 1, ht = !lap && it != 1;
+            // The link W_d(n) of the hop d_x = ix - 1, as applied, and the copy site of its neighbour: for
+            // rc < 13 (and rc = 13 with d_x = -1) W_d is stored at the own site, else it is the adjoint of the
+            // link stored at n + d, which the window already holds transposed and conjugated (CS: only the
+            // thread's row ca of W_d)
+            auto hop_link = [&](int ix, cx<R> (&l)[NA][NC]) __attribute__((always_inline)) {
                 const int cn = SEG ? static_cast<int>(j) + ix : wrap(static_cast<int>(j) + ix - 1, g.nx);
-                const S* nbp = at(cn);
-                if (rc == 13 && ix == 1) {  // the centre: (m - lambda_0 / 2) u(n), plus the clover term
-#pragma unroll
-                    for (int k = 0; k < RB; ++k)
-#pragma unroll
-                        for (int a = 0; a < NA; ++a)
-#pragma unroll
-                            for (int s = 0; s < 4; ++s) {
-                                const cx<R> v = io<R, S>::ld(nbp + ((CS ? ca : a) * 4 + s) * nv + k);
-                                acc[k][a][s].re += diag * v.re;
-                                acc[k][a][s].im += diag * v.im;
-                            }
-                    if constexpr (!CS)  // the launcher takes the colour-split form only without a clover field
-                        if (clov) clover_add<NC, RB>(acc, nbp, nv, clov + (own_start + x) * clover_reals<NC>());
-                    continue;
-                }
-                // W_d(n): stored at the own site (rc < 13, or rc = 13 with d_x = -1), else the
-                // adjoint of the stored link at n + d
-                // l holds the stored matrix; for the adjoint directions W_d(n) = l^+, applied below
-                // with conjugating multiply-adds instead of an explicit conjugate
-                // (CS: only the thread's row ca of W_d, i.e. row ca of l, or column ca for the adjoints)
-                cx<R> l[NA][NC];
                 const bool adj = rc > 13 || (rc == 13 && ix == 2);
                 const G* lp = lwin + (adj ? cn : static_cast<int>(j) + OFF) * LW +
-                              (rc < 13 ? ix : (rc == 13 ? 2 : 2 - ix)) * L;
+                              (rc < 13 ? ix : (rc == 13 ? (ix == 2 ? 0 : 2) : 2 - ix)) * L;
 #pragma unroll
                 for (int a = 0; a < NA; ++a)
 #pragma unroll
-                    for (int b = 0; b < NC; ++b) {
-                        if constexpr (CS)
-                            l[a][b] = io<R, G>::ld(lp + (adj ? b * NC + ca : ca * NC + b));
-                        else
-                            l[a][b] = io<R, G>::ld(lp + a * NC + b);
-                    }
-                const R* sv = spin_table<R>(DAG ? 1 : 0, flip, 27 * it + 9 * iz + 3 * iy + ix);
-                const R lh = sv[0], q1 = sv[1], q2 = sv[2], q3 = sv[3], q4 = sv[4];
-                if constexpr (CS) {
-                    // one colour row: the neighbour's colour components are consumed one at a time
-                    cx<R> ch[4] = {{R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}};
+                    for (int b = 0; b < NC; ++b) l[a][b] = io<R, G>::ld(lp + ((CS ? ca : a) * NC + b));
+                return cn;
+            };
+            // c[a] += (W_d u(n + d))_a, one neighbour colour at a time
+            auto hop_add = [&](int ix, cx<R> (&c)[NA][4]) __attribute__((always_inline)) {
+                cx<R> l[NA][NC];
+                const S* nbp = at(hop_link(ix, l));
 #pragma unroll
-                    for (int b = 0; b < NC; ++b) {
-                        cx<R> pb[4];
+                for (int b = 0; b < NC; ++b) {
+                    cx<R> pb[4];
 #pragma unroll
-                        for (int s = 0; s < 4; ++s) pb[s] = io<R, S>::ld(nbp + (b * 4 + s) * nv);
+                    for (int s = 0; s < 4; ++s) pb[s] = io<R, S>::ld(nbp + (b * 4 + s) * nv);
 #pragma unroll
-                        for (int s = 0; s < 4; ++s) {
-                            if (adj)
-                                cfma_conj(ch[s], l[0][b], pb[s]);
-                            else
-                                cfma(ch[s], l[0][b], pb[s]);
-                        }
-                    }
-                    spin_accumulate(acc[0][0], ch, lh, q1, q2, q3, q4, !lap && ix != 1, !lap && iy != 1,
-                                    !lap && iz != 1, !lap && it != 1);
-                    continue;
+                    for (int a = 0; a < NA; ++a)
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) cfma(c[a][s], l[a][b], pb[s]);
                 }
+            };
+            // d_x = 0: the centre (rc = 13), else a hop of its own
+            if (rc == 13) {  // (m - lambda_0 / 2) u(n), plus the clover term
+                const S* nbp = at(static_cast<int>(j) + OFF);
 #pragma unroll
-                for (int k = 0; k < RB; ++k) {
-                    cx<R> p[NC][4];
+                for (int a = 0; a < NA; ++a)
 #pragma unroll
-                    for (int b = 0; b < NC; ++b)
-#pragma unroll
-                        for (int s = 0; s < 4; ++s) p[b][s] = io<R, S>::ld(nbp + (b * 4 + s) * nv + k);
-#pragma unroll
-                    for (int a = 0; a < NA; ++a) {
-                        cx<R> ch[4] = {{R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}};
-                        if (adj) {  // (l^+)[a][b] = conj(l[b][a]); CS: l[0][b] already holds l[b][ca]
-#pragma unroll
-                            for (int b = 0; b < NC; ++b)
-#pragma unroll
-                                for (int s = 0; s < 4; ++s) cfma_conj(ch[s], CS ? l[a][b] : l[b][a], p[b][s]);
-                        } else {
-#pragma unroll
-                            for (int b = 0; b < NC; ++b)
-#pragma unroll
-                                for (int s = 0; s < 4; ++s) cfma(ch[s], l[a][b], p[b][s]);
-                        }
-                        spin_accumulate(acc[k][a], ch, lh, q1, q2, q3, q4, !lap && ix != 1, !lap && iy != 1,
-                                        !lap && iz != 1, !lap && it != 1);
+                    for (int s = 0; s < 4; ++s) {
+                        const cx<R> v = io<R, S>::ld(nbp + ((CS ? ca : a) * 4 + s) * nv);
+                        acc[0][a][s].re += diag * v.re;
+                        acc[0][a][s].im += diag * v.im;
                     }
-                }
+                if constexpr (!CS)  // the launcher takes the colour-split form only without a clover field
+                    if (clov) clover_add<NC, RB>(acc, nbp, nv, clov + (own_start + x) * clover_reals<NC>());
+            } else {
+                const R* sv = spin_table<R>(DAG ? 1 : 0, 0, dir0 + 1);
+                cx<R> c[NA][4] = {};
+                hop_add(1, c);
+#pragma unroll
+                for (int a = 0; a < NA; ++a)
+                    spin_accumulate(acc[0][a], c[a], sv[0], sv[1], sv[2], sv[3], sv[4], false, hy, hz, ht);
             }
+            // d_x = -1 and +1 carry the same spin factor up to the sign of the gamma_x term:
+            // S_- chi_- + S_+ chi_+ = S_+ (chi_- + chi_+) + 2 q_x(-) gamma_x chi_-, so both hops share one
+            // accumulator and one application of the lambda and gamma_y..gamma_t terms
+            const R* sm = spin_table<R>(DAG ? 1 : 0, 0, dir0);
+            const R* sp = spin_table<R>(DAG ? 1 : 0, 0, dir0 + 2);
+            cx<R> c[NA][4] = {};
+            hop_add(0, c);
+            if (!lap) {
+                const R qx2 = R(2) * sm[1];
+#pragma unroll
+                for (int a = 0; a < NA; ++a) gamma_x_accumulate(acc[0][a], c[a], qx2);
+            }
+            hop_add(2, c);
+#pragma unroll
+            for (int a = 0; a < NA; ++a)
+                spin_accumulate(acc[0][a], c[a], sp[0], sp[1], sp[2], sp[3], sp[4], !lap, hy, hz, ht);
         }
     }
     __syncthreads();
