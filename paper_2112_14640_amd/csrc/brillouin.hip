@@ -345,9 +345,10 @@ __global__ __launch_bounds__(256) void brillouin_kernel(const typename P::G* __r
 // row serves d_x = -1 as stored and d_x = +1 as the adjoint at x + 1.  The window holds each link as
 // applied: adjoints transposed and conjugated, and the fermion sign of a t step across the boundary
 // folded in, so that every hop is the same plain product.  The next row copy is in flight (in
-// registers) while the current one is consumed.  Per row, the hop d_x = 0 is applied on its own, and
-// the hops d_x = -1 and +1, whose spin factors differ only in the sign of the gamma_x term, share one
-// accumulator (a third fewer spin-factor multiply-adds than one hop at a time).  Three waves per SIMD
+// registers) while the current one is consumed.  The three hops of a row, whose spin factors share
+// their gamma_y..gamma_t terms up to fixed ratios, go into one accumulator (15432 instead of 18648
+// multiply-adds per site and RHS with N_c = 3, the App. E count unchanged; the colour-split form
+// shares it between the d_x = -1 and +1 hops only).  Three waves per SIMD
 // cap the registers at 168 (FP32 and BF16 fit, the segmented forms spill a few values); FP64, whose
 // operands take twice the registers, takes the colour-split form (CS) at three waves per SIMD.
 template <int NC, int RB, bool DAG, class P, int NVC, bool SEG, bool CS = false>
@@ -428,7 +429,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
     u32x4 pre[PER];
     u32x4 hpre[2];
     G lpre[PERL];
-    uint32_t lneg = 0;  // bits 2k, 2k + 1: negate the real, imaginary part of lpre[k] when it is stored
+    // bits 3k, 3k + 1: negate the real, imaginary part of lpre[k] when it is stored; bit 3k + 2: scale it by 4
+    uint32_t lneg = 0;
     // row copies and link windows are buffer loads over one lattice row: a scalar base per row, 32-bit
     // offsets per lane (a read past the row returns zero instead of touching memory)
     const uint32_t row_bytes = static_cast<uint32_t>(g.nx) * rt.units * 16u;
@@ -471,7 +473,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
                 const int xs = SEG ? wrap(x0 - 1 + static_cast<int>(sx), g.nx) : static_cast<int>(sx);
                 lpre[k] = buffer_load_unit<G>(rw, ((static_cast<uint32_t>(xs) * 40u + wb) * L + from) *
                                                       static_cast<uint32_t>(sizeof(G)), 0u);
-                lneg |= (bflip ? 1u << (2 * k) : 0u) | (adj != bflip ? 2u << (2 * k) : 0u);
+                // slot 1 of a row other than the centre row is the d_x = 0 hop, stored times 4 for the
+                // three-hop accumulation (not in the colour-split form)
+                lneg |= ((bflip ? 1u : 0u) | (adj != bflip ? 2u : 0u) | (!CS && rc != 13 && slot == 1 ? 4u : 0u))
+                        << (3 * k);
             }
         }
     };
@@ -504,8 +509,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
             const uint32_t u = k * static_cast<uint32_t>(rt.threads) + tt;
             if (u < nlink) {
                 G v = lpre[k];
-                if (negm & (1u << (2 * k))) v.x = -v.x;
-                if (negm & (2u << (2 * k))) v.y = -v.y;
+                if (negm & (1u << (3 * k))) v.x = -v.x;
+                if (negm & (2u << (3 * k))) v.y = -v.y;
+                if (negm & (4u << (3 * k))) {
+                    v.x *= 4;
+                    v.y *= 4;
+                }
                 lwin[u] = v;
             }
         }
@@ -547,8 +556,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
                         for (int s = 0; s < 4; ++s) cfma(c[a][s], l[a][b], pb[s]);
                 }
             };
-            // d_x = 0: the centre (rc = 13), else a hop of its own
-            if (rc == 13) {  // (m - lambda_0 / 2) u(n), plus the clover term
+            if (rc == 13) {  // d_x = 0 is the centre: (m - lambda_0 / 2) u(n), plus the clover term
                 const S* nbp = at(static_cast<int>(j) + OFF);
 #pragma unroll
                 for (int a = 0; a < NA; ++a)
@@ -560,30 +568,54 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
                     }
                 if constexpr (!CS)  // the launcher takes the colour-split form only without a clover field
                     if (clov) clover_add<NC, RB>(acc, nbp, nv, clov + (own_start + x) * clover_reals<NC>());
-            } else {
-                const R* sv = spin_table<R>(DAG ? 1 : 0, 0, dir0 + 1);
-                cx<R> c[NA][4] = {};
-                hop_add(1, c);
-#pragma unroll
-                for (int a = 0; a < NA; ++a)
-                    spin_accumulate(acc[0][a], c[a], sv[0], sv[1], sv[2], sv[3], sv[4], false, hy, hz, ht);
             }
-            // d_x = -1 and +1 carry the same spin factor up to the sign of the gamma_x term:
-            // S_- chi_- + S_+ chi_+ = S_+ (chi_- + chi_+) + 2 q_x(-) gamma_x chi_-, so both hops share one
-            // accumulator and one application of the lambda and gamma_y..gamma_t terms
             const R* sm = spin_table<R>(DAG ? 1 : 0, 0, dir0);
             const R* sp = spin_table<R>(DAG ? 1 : 0, 0, dir0 + 2);
-            cx<R> c[NA][4] = {};
-            hop_add(0, c);
-            if (!lap) {
-                const R qx2 = R(2) * sm[1];
+            if constexpr (CS) {
+                // the colour-split form runs fastest with the d_x = 0 hop on its own and the d_x = -1, +1
+                // hops sharing one accumulator: S_- chi_- + S_+ chi_+ = S_+ (chi_- + chi_+) + 2 q_- gamma_x chi_-
+                if (rc != 13) {
+                    const R* sv = spin_table<R>(DAG ? 1 : 0, 0, dir0 + 1);
+                    cx<R> c0[NA][4] = {};
+                    hop_add(1, c0);
 #pragma unroll
-                for (int a = 0; a < NA; ++a) gamma_x_accumulate(acc[0][a], c[a], qx2);
+                    for (int a = 0; a < NA; ++a)
+                        spin_accumulate(acc[0][a], c0[a], sv[0], sv[1], sv[2], sv[3], sv[4], false, hy, hz, ht);
+                }
+                cx<R> c[NA][4] = {};
+                hop_add(0, c);
+                if (!lap) {
+#pragma unroll
+                    for (int a = 0; a < NA; ++a) gamma_x_accumulate(acc[0][a], c[a], R(2) * sm[1]);
+                }
+                hop_add(2, c);
+#pragma unroll
+                for (int a = 0; a < NA; ++a)
+                    spin_accumulate(acc[0][a], c[a], sp[0], sp[1], sp[2], sp[3], sp[4], !lap, hy, hz, ht);
+            } else {
+                // The three hops of a row share one accumulator c.  With k the number of non-zero components of
+                // d_x = +-1 (and k - 1 for d_x = 0), S_pm = -l + R pm q gamma_x with l = lambda_k / 2 and
+                // R = sum over y, z, t of rho_k d_mu gamma_mu; the d_x = 0 hop has S_0 = -2 l + 4 R (rho and
+                // lambda fall by 4 and 2 per unit of k).  So S_- chi_- + S_+ chi_+ + S_0 chi_0 =
+                //   2 q_- gamma_x chi_- + (q_+ gamma_x - l / 2) (chi_- + chi_+) + (R - l / 2) (chi_- + chi_+ + 4 chi_0),
+                // taken as c = chi_-, then c += chi_+, then c += 4 chi_0 (its link is stored times 4).  In the
+                // centre row the last step is -l / 2 alone.
+                const R lq = R(0.5) * sp[0];
+                cx<R> c[NA][4] = {};
+                hop_add(0, c);
+                if (!lap) {
+#pragma unroll
+                    for (int a = 0; a < NA; ++a) gamma_x_accumulate(acc[0][a], c[a], R(2) * sm[1]);
+                }
+                hop_add(2, c);
+#pragma unroll
+                for (int a = 0; a < NA; ++a)
+                    spin_accumulate(acc[0][a], c[a], lq, sp[1], sp[2], sp[3], sp[4], !lap, false, false, false);
+                if (rc != 13) hop_add(1, c);
+#pragma unroll
+                for (int a = 0; a < NA; ++a)
+                    spin_accumulate(acc[0][a], c[a], lq, sp[1], sp[2], sp[3], sp[4], false, hy, hz, ht);
             }
-            hop_add(2, c);
-#pragma unroll
-            for (int a = 0; a < NA; ++a)
-                spin_accumulate(acc[0][a], c[a], sp[0], sp[1], sp[2], sp[3], sp[4], !lap, hy, hz, ht);
         }
     }
     __syncthreads();
