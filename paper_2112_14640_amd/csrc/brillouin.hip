@@ -366,7 +366,6 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
     constexpr int PER = CS ? RowUnits<NC, RB, P>::PER / NC : RowUnits<NC, RB, P>::PER;
     constexpr int NA = CS ? 1 : NC;  // colour rows per thread
     constexpr int L = NC * NC;
-    constexpr int LW = 3 * L;  // link-window elements per site
     extern __shared__ __align__(16) u32x4 rtile[];
     if constexpr (NVC > 0) nv = NVC;
 
@@ -398,9 +397,23 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
     // (c = x, S = n_x, neighbours wrap inside it).  Then the link window.
     constexpr int OFF = SEG ? 1 : 0;  // copy site of the segment's first site
     const int SC = rt.S + 2 * OFF;    // sites per copy
-    G* lwin = reinterpret_cast<G*>(rtile + SC * (rt.units + 1));  // SC * LW link elements
-    const uint32_t nlink = static_cast<uint32_t>(SC) * LW;
-    constexpr int PERL = CS ? 2 : 4;  // link elements per thread (checked at launch)
+    // the link window, slot-major: lwin[slot][copy site][L], slot = one of the three stored directions
+    G* lwin = reinterpret_cast<G*>(rtile + SC * (rt.units + 1));
+    const uint32_t WS = static_cast<uint32_t>(SC) * L;  // elements per slot
+    // Each load instruction of the window covers one slot: KPS loads per slot, each lane taking entry
+    // q * threads + tt of it (checked at launch: SC * L <= KPS * threads); lanes past the slot repeat its
+    // last entry and store nothing.  The slot's transposition, sign and scale are then wave-uniform.
+    constexpr int KPS = NC >= 4 ? 2 : 1;
+    constexpr int PERL = 3 * KPS;
+    uint32_t woff[KPS], wofft[KPS];  // the lane's element in a stored direction block: as stored, transposed
+#pragma unroll
+    for (int q = 0; q < KPS; ++q) {
+        const uint32_t e = min(q * static_cast<uint32_t>(rt.threads) + tt, WS - 1u);
+        const uint32_t sx = e / L, ab = e - sx * L;
+        const uint32_t xs = SEG ? static_cast<uint32_t>(wrap(x0 - 1 + static_cast<int>(sx), g.nx)) : sx;
+        woff[q] = xs * 40u * L + ab;
+        wofft[q] = xs * 40u * L + (ab % NC) * NC + ab / NC;
+    }
     uint32_t slot[PER];      // main units: the S sites of the segment, copy sites 1 .. S
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
@@ -429,8 +442,6 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
     u32x4 pre[PER];
     u32x4 hpre[2];
     G lpre[PERL];
-    // bits 3k, 3k + 1: negate the real, imaginary part of lpre[k] when it is stored; bit 3k + 2: scale it by 4
-    uint32_t lneg = 0;
     // row copies and link windows are buffer loads over one lattice row: a scalar base per row, 32-bit
     // offsets per lane (a read past the row returns zero instead of touching memory)
     const uint32_t row_bytes = static_cast<uint32_t>(g.nx) * rt.units * 16u;
@@ -450,34 +461,16 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
         const int64_t lstart = rc <= 13 ? own_start : start;
         const int wb = rc < 13 ? dir0 : (rc == 13 ? 37 : 78 - dir0);
         const auto rw = raw_buffer(W + lstart * 40 * L, wrow_bytes);
-        // the fermion sign of a t step across the boundary rides on the row's links (all three hops of a
-        // row copy take the same t step)
-        const int itf = rc / 9;
-        const bool bflip = g.apbc && ((itf == 0 && ct == 0) || (itf == 2 && ct == g.nt - 1));
-        lneg = 0;
+        // window slot `slot` holds W_d(n) as applied: for rc > 13 every slot is the adjoint of the stored
+        // link (element (a, b) <- conj of stored (b, a)); for rc = 13 slot 2 holds direction 39 as stored
+        // and slot 0 its adjoint
 #pragma unroll
         for (int k = 0; k < PERL; ++k) {
-            // every lane loads (lanes past the window repeat its last element, which they do not store):
-            // a conditional load would be copied out of its register and waited for here
-            const uint32_t u = min(k * static_cast<uint32_t>(rt.threads) + tt, nlink - 1u);
-            {
-                const uint32_t sx = u / LW;
-                const uint32_t e = u - sx * LW;
-                const uint32_t slot = e / L, ab = e - slot * L;
-                // window slot `slot` holds W_d(n) as applied: for rc > 13 every slot is the adjoint of the
-                // stored link (element (a, b) <- conj of stored (b, a)); for rc = 13 slot 2 holds direction
-                // 39 as stored and slot 0 its adjoint
-                const bool adj = rc > 13 || (rc == 13 && slot == 0);
-                const uint32_t from = (rc == 13 && slot == 0 ? 2u : slot) * L +
-                                      (adj ? (ab % NC) * NC + ab / NC : ab);
-                const int xs = SEG ? wrap(x0 - 1 + static_cast<int>(sx), g.nx) : static_cast<int>(sx);
-                lpre[k] = buffer_load_unit<G>(rw, ((static_cast<uint32_t>(xs) * 40u + wb) * L + from) *
-                                                      static_cast<uint32_t>(sizeof(G)), 0u);
-                // slot 1 of a row other than the centre row is the d_x = 0 hop, stored times 4 for the
-                // three-hop accumulation (not in the colour-split form)
-                lneg |= ((bflip ? 1u : 0u) | (adj != bflip ? 2u : 0u) | (!CS && rc != 13 && slot == 1 ? 4u : 0u))
-                        << (3 * k);
-            }
+            const int slot = k / KPS, q = k % KPS;
+            const bool adj = rc > 13 || (rc == 13 && slot == 0);
+            const uint32_t from = (adj ? wofft[q] : woff[q]) +
+                                  static_cast<uint32_t>(wb + (rc == 13 && slot == 0 ? 2 : slot)) * L;
+            lpre[k] = buffer_load_unit<G>(rw, from * static_cast<uint32_t>(sizeof(G)), 0u);
         }
     };
     auto at = [&](int c) __attribute__((always_inline)) {
@@ -500,22 +493,30 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
 #pragma unroll
         for (int q = 0; q < 2; ++q)
             if (SEG && halo[q]) rtile[hslot[q]] = hpre[q];
-        // the sign changes stay here, after the barrier: taken at the loads, they would wait for the
-        // prefetch there and serialise it with the row's arithmetic
-        uint32_t negm = lneg;
-        asm volatile("" : "+v"(negm));
+        // The window as applied: the adjoint's conjugation, the fermion sign of a t step across the boundary
+        // (all three hops of a row take the same t step) and, for the three-hop accumulation below, the
+        // d_x = 0 hop times 4 (slot 1 outside the centre row) are factors of the real and imaginary parts,
+        // uniform per slot.  They are taken from a copy of rc made opaque here, after the barrier: taken at
+        // the loads, they would make the compiler wait for the prefetch there.
+        {
+            int rs = rc;
+            asm volatile("" : "+s"(rs));
+            const int its = rs / 9;
+            const bool bflip = g.apbc && ((its == 0 && ct == 0) || (its == 2 && ct == g.nt - 1));
 #pragma unroll
-        for (int k = 0; k < PERL; ++k) {
-            const uint32_t u = k * static_cast<uint32_t>(rt.threads) + tt;
-            if (u < nlink) {
-                G v = lpre[k];
-                if (negm & (1u << (3 * k))) v.x = -v.x;
-                if (negm & (2u << (3 * k))) v.y = -v.y;
-                if (negm & (4u << (3 * k))) {
-                    v.x *= 4;
-                    v.y *= 4;
+            for (int k = 0; k < PERL; ++k) {
+                const int slot = k / KPS, q = k % KPS;
+                const bool adj = rs > 13 || (rs == 13 && slot == 0);
+                const R sc = (!CS && slot == 1 && rs != 13) ? R(4) : R(1);
+                const R fx = bflip ? -sc : sc;
+                const R fy = adj != bflip ? -sc : sc;
+                const uint32_t u = q * static_cast<uint32_t>(rt.threads) + tt;
+                if (u < WS) {
+                    G v = lpre[k];
+                    v.x *= fx;
+                    v.y *= fy;
+                    lwin[slot * WS + u] = v;
                 }
-                lwin[u] = v;
             }
         }
         __syncthreads();
@@ -533,8 +534,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
             auto hop_link = [&](int ix, cx<R> (&l)[NA][NC]) __attribute__((always_inline)) {
                 const int cn = SEG ? static_cast<int>(j) + ix : wrap(static_cast<int>(j) + ix - 1, g.nx);
                 const bool adj = rc > 13 || (rc == 13 && ix == 2);
-                const G* lp = lwin + (adj ? cn : static_cast<int>(j) + OFF) * LW +
-                              (rc < 13 ? ix : (rc == 13 ? (ix == 2 ? 0 : 2) : 2 - ix)) * L;
+                const G* lp = lwin + (rc < 13 ? ix : (rc == 13 ? (ix == 2 ? 0 : 2) : 2 - ix)) * WS +
+                              (adj ? cn : static_cast<int>(j) + OFF) * L;
 #pragma unroll
                 for (int a = 0; a < NA; ++a)
 #pragma unroll
@@ -686,7 +687,7 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
     auto fits = [&](int d, int cap) {
         const int64_t th = static_cast<int64_t>(d) * nrg;
         return a.g.nx % d == 0 && th <= cap && th >= 64 && units <= th &&
-               static_cast<int64_t>(d + 2) * 3 * NC * NC <= (kSplit ? 2 : 4) * th;
+               static_cast<int64_t>(d + 2) * NC * NC <= (NC >= 4 ? 2 : 1) * th;
     };
     int seg = 0;
     for (int cap : {256, 512}) {
