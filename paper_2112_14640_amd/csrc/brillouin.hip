@@ -673,34 +673,50 @@ double centre_coefficient(const StencilArgs& a) {
 template <int NC, int RB, class P>
 bool launch_rows(const StencilArgs& a, hipStream_t st) {
     using S = typename P::S;
+    using R = typename P::R;
     const size_t block_bytes = static_cast<size_t>(NC) * 4 * a.nv * sizeof(S);
     if (block_bytes % 16 != 0 || !tile_aligned(a)) return false;
     const int units = static_cast<int>(block_bytes / 16);
-    // FP64 takes the colour-split form (one colour row of one RHS per thread), which keeps its registers
-    // under the cap of three waves per SIMD; it carries no clover term (that case keeps the direct kernel)
-    constexpr bool kSplit = sizeof(typename P::R) == 8 && RB == 1;
-    if (kSplit && a.clover) return false;
-    const int nrg = kSplit ? a.nv * NC : a.nv / RB;
+    // FP64: one thread per (site, RHS) where its two waves per SIMD hold the registers (N_c <= 3, a few
+    // spills at N_c = 3), else the colour-split form (one colour row of one RHS per thread, three waves
+    // per SIMD), which carries no clover term (that case keeps the direct kernel)
+    constexpr bool kFP64 = sizeof(R) == 8;
     const int64_t rows = a.g.vol / a.g.nx;
     // segment: the largest divisor of n_x with at most 256 threads (at most 512 if none), at least
     // 64 threads and enough threads for the two halo sites (two units each) and the link window
-    auto fits = [&](int d, int cap) {
-        const int64_t th = static_cast<int64_t>(d) * nrg;
-        return a.g.nx % d == 0 && th <= cap && th >= 64 && units <= th &&
-               static_cast<int64_t>(d + 2) * NC * NC <= (NC >= 4 ? 2 : 1) * th;
+    auto plan = [&](bool cs, int& seg, size_t& lds) {
+        const int nrg = cs ? a.nv * NC : a.nv / RB;
+        auto fits = [&](int d, int cap) {
+            const int64_t th = static_cast<int64_t>(d) * nrg;
+            return a.g.nx % d == 0 && th <= cap && th >= 64 && units <= th &&
+                   static_cast<int64_t>(d + 2) * NC * NC <= (NC >= 4 ? 2 : 1) * th;
+        };
+        seg = 0;
+        for (int cap : {256, 512}) {
+            for (int d = a.g.nx; d >= 1 && !seg; --d)
+                if (fits(d, cap)) seg = d;
+            if (seg) break;
+        }
+        if (seg == 0) return false;
+        const int sc = seg + (seg != a.g.nx ? 2 : 0);  // sites per copy
+        lds = static_cast<size_t>(sc) * (units + 1) * 16 +
+              static_cast<size_t>(sc) * 3 * NC * NC * sizeof(typename P::G);
+        return lds <= 64 * 1024;
     };
     int seg = 0;
-    for (int cap : {256, 512}) {
-        for (int d = a.g.nx; d >= 1 && !seg; --d)
-            if (fits(d, cap)) seg = d;
-        if (seg) break;
+    size_t lds = 0;
+    bool cs = false;
+    if (!kFP64 || NC <= 3) {
+        if (!plan(false, seg, lds)) {
+            if (!kFP64 || a.clover || RB != 1 || !plan(true, seg, lds)) return false;
+            cs = true;
+        }
+    } else {
+        if (a.clover || RB != 1 || !plan(true, seg, lds)) return false;
+        cs = true;
     }
-    if (seg == 0) return false;
     const bool segmented = seg != a.g.nx;
-    const int sc = seg + (segmented ? 2 : 0);  // sites per copy
-    const size_t lds = static_cast<size_t>(sc) * (units + 1) * 16 +
-                       static_cast<size_t>(sc) * 3 * NC * NC * sizeof(typename P::G);
-    if (lds > 64 * 1024) return false;
+    const int nrg = cs ? a.nv * NC : a.nv / RB;
     if (!ensure_spin_table()) return false;  // the direct kernel needs no table
     RowTile rt{};
     rt.R = 1;
@@ -718,7 +734,6 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
     if (!row_order(4, a.g, rt)) return false;
     const int block = (rt.threads + 63) / 64 * 64;
     const dim3 grid(static_cast<unsigned>(grid_blocks_x8(rt.ntiles, 1)));
-    using R = typename P::R;
     const R diag = static_cast<R>(centre_coefficient(a));
     auto W = static_cast<const typename P::G*>(a.gauge);
     auto in = static_cast<const S*>(a.in);
@@ -728,36 +743,36 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, grid, dim3(block), lds, st, W, in, out, diag, a.g, a.nv, rt, clov, lap);
     };
-    auto pick = [&](auto seg_c) {
+    auto pick = [&](auto seg_c, auto cs_c) {
         constexpr bool SG = decltype(seg_c)::value;
-        if constexpr (kSplit) {
-            if (a.nv == 12) {
-                if (a.dagger)
-                    go(brillouin_rows_kernel<NC, RB, true, P, 12, SG, true>);
-                else
-                    go(brillouin_rows_kernel<NC, RB, false, P, 12, SG, true>);
-            } else {
-                if (a.dagger)
-                    go(brillouin_rows_kernel<NC, RB, true, P, 0, SG, true>);
-                else
-                    go(brillouin_rows_kernel<NC, RB, false, P, 0, SG, true>);
-            }
-        } else if (a.nv == 12 && RB == 1) {
+        constexpr bool C = decltype(cs_c)::value;
+        if (a.nv == 12 && RB == 1) {
             if (a.dagger)
-                go(brillouin_rows_kernel<NC, RB, true, P, 12, SG>);
+                go(brillouin_rows_kernel<NC, RB, true, P, 12, SG, C>);
             else
-                go(brillouin_rows_kernel<NC, RB, false, P, 12, SG>);
+                go(brillouin_rows_kernel<NC, RB, false, P, 12, SG, C>);
         } else {
             if (a.dagger)
-                go(brillouin_rows_kernel<NC, RB, true, P, 0, SG>);
+                go(brillouin_rows_kernel<NC, RB, true, P, 0, SG, C>);
             else
-                go(brillouin_rows_kernel<NC, RB, false, P, 0, SG>);
+                go(brillouin_rows_kernel<NC, RB, false, P, 0, SG, C>);
         }
     };
-    if (segmented)
-        pick(std::true_type{});
-    else
-        pick(std::false_type{});
+    auto pick_seg = [&](auto cs_c) {
+        if (segmented)
+            pick(std::true_type{}, cs_c);
+        else
+            pick(std::false_type{}, cs_c);
+    };
+    if constexpr (kFP64) {
+        if (cs) {
+            pick_seg(std::true_type{});
+            return true;
+        }
+        if constexpr (NC <= 3) pick_seg(std::false_type{});
+    } else {
+        pick_seg(std::false_type{});
+    }
     return true;
 }
 
