@@ -461,15 +461,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
         const int64_t lstart = rc <= 13 ? own_start : start;
         const int wb = rc < 13 ? dir0 : (rc == 13 ? 37 : 78 - dir0);
         const auto rw = raw_buffer(W + lstart * 40 * L, wrow_bytes);
-        // window slot `slot` holds W_d(n) as applied: for rc > 13 every slot is the adjoint of the stored
+        // window slot ws holds W_d(n) as applied: for rc > 13 every slot is the adjoint of the stored
         // link (element (a, b) <- conj of stored (b, a)); for rc = 13 slot 2 holds direction 39 as stored
         // and slot 0 its adjoint
 #pragma unroll
         for (int k = 0; k < PERL; ++k) {
-            const int slot = k / KPS, q = k % KPS;
-            const bool adj = rc > 13 || (rc == 13 && slot == 0);
+            const int ws = k / KPS, q = k % KPS;
+            const bool adj = rc > 13 || (rc == 13 && ws == 0);
             const uint32_t from = (adj ? wofft[q] : woff[q]) +
-                                  static_cast<uint32_t>(wb + (rc == 13 && slot == 0 ? 2 : slot)) * L;
+                                  static_cast<uint32_t>(wb + (rc == 13 && ws == 0 ? 2 : ws)) * L;
             lpre[k] = buffer_load_unit<G>(rw, from * static_cast<uint32_t>(sizeof(G)), 0u);
         }
     };
@@ -505,9 +505,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
             const bool bflip = g.apbc && ((its == 0 && ct == 0) || (its == 2 && ct == g.nt - 1));
 #pragma unroll
             for (int k = 0; k < PERL; ++k) {
-                const int slot = k / KPS, q = k % KPS;
-                const bool adj = rs > 13 || (rs == 13 && slot == 0);
-                const R sc = (!CS && slot == 1 && rs != 13) ? R(4) : R(1);
+                const int ws = k / KPS, q = k % KPS;
+                const bool adj = rs > 13 || (rs == 13 && ws == 0);
+                const R sc = (!CS && ws == 1 && rs != 13) ? R(4) : R(1);
                 const R fx = bflip ? -sc : sc;
                 const R fy = adj != bflip ? -sc : sc;
                 const uint32_t u = q * static_cast<uint32_t>(rt.threads) + tt;
@@ -515,7 +515,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
                     G v = lpre[k];
                     v.x *= fx;
                     v.y *= fy;
-                    lwin[slot * WS + u] = v;
+                    lwin[ws * WS + u] = v;
                 }
             }
         }
