@@ -351,6 +351,16 @@ __global__ __launch_bounds__(256) void brillouin_kernel(const typename P::G* __r
 // shares it between the d_x = -1 and +1 hops only).  Three waves per SIMD
 // cap the registers at 168 (FP32 and BF16 fit, the segmented forms spill a few values); FP64, whose
 // operands take twice the registers, takes the colour-split form (CS) at three waves per SIMD.
+// Padding (16-byte units) after each site of a row copy in LDS.  The threads of a wave read one element
+// of consecutive RHS at a time, site after site; with the site stride congruent to the span of one site's
+// RHS run (span dwords) modulo the 64 LDS banks, the runs of consecutive sites fall on consecutive banks
+// and a read is free of bank conflicts.  One unit when the span is not a whole number of units.
+__host__ __device__ inline uint32_t row_pad(uint32_t units, uint32_t span) {
+    if (span % 4u != 0) return 1u;
+    const uint32_t p = ((span % 64u) + 64u - (4u * units) % 64u) % 64u / 4u;
+    return p == 0 ? 16u : p;
+}
+
 template <int NC, int RB, bool DAG, class P, int NVC, bool SEG, bool CS = false>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(typename P::R) == 8 && !CS ? 2 : 3))) void brillouin_rows_kernel(const typename P::G* __restrict__ W,
                                                              const typename P::S* __restrict__ in,
@@ -398,7 +408,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
     constexpr int OFF = SEG ? 1 : 0;  // copy site of the segment's first site
     const int SC = rt.S + 2 * OFF;    // sites per copy
     // the link window, slot-major: lwin[slot][copy site][L], slot = one of the three stored directions
-    G* lwin = reinterpret_cast<G*>(rtile + SC * (rt.units + 1));
+    const uint32_t PADU = row_pad(rt.units, static_cast<uint32_t>(nv) * static_cast<uint32_t>(sizeof(S)) / 4u);
+    const uint32_t SU = rt.units + PADU;  // units per site of the row copy
+    G* lwin = reinterpret_cast<G*>(rtile + SC * SU);
     const uint32_t WS = static_cast<uint32_t>(SC) * L;  // elements per slot
     // Each load instruction of the window covers one slot: KPS loads per slot, each lane taking entry
     // q * threads + tt of it (checked at launch: SC * L <= KPS * threads); lanes past the slot repeat its
@@ -418,7 +430,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const uint32_t u = k * static_cast<uint32_t>(rt.threads) + tt;
-        slot[k] = u + fast_div(u, rt.magic_units) + OFF * (rt.units + 1);
+        slot[k] = u + fast_div(u, rt.magic_units) * PADU + OFF * SU;
     }
     // halo units h = tt and tt + threads (< 2 units) copy the sites x0 - 1 (copy site 0) and x0 + S
     // (copy site S + 1)
@@ -431,7 +443,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
         halo[q] = SEG && h < 2u * rt.units;
         const uint32_t hs = h < static_cast<uint32_t>(rt.units) ? 0u : 1u;
         const uint32_t hcu = h - hs * rt.units;
-        hslot[q] = (hs ? rt.S + 1 : 0) * (rt.units + 1) + hcu;
+        hslot[q] = (hs ? rt.S + 1 : 0) * SU + hcu;
         hsrc[q] = static_cast<uint32_t>(hs ? wrap(x0 + rt.S, g.nx) : wrap(x0 - 1, g.nx)) * rt.units + hcu;
     }
     auto row_start = [&](int rc) __attribute__((always_inline)) {
@@ -474,7 +486,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
         }
     };
     auto at = [&](int c) __attribute__((always_inline)) {
-        return reinterpret_cast<const S*>(rtile + c * (rt.units + 1)) + col;
+        return reinterpret_cast<const S*>(rtile + c * SU) + col;
     };
 
     cx<R> acc[RB][NA][4];
@@ -632,7 +644,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(type
     __syncthreads();
     u32x4* dst = reinterpret_cast<u32x4*>(out) + (own_start + x0) * rt.units;
     const uint32_t total = static_cast<uint32_t>(rt.S) * rt.units;
-    for (uint32_t u = tid; u < total; u += blockDim.x) dst[u] = rtile[u + fast_div(u, rt.magic_units) + OFF * (rt.units + 1)];
+    for (uint32_t u = tid; u < total; u += blockDim.x) dst[u] = rtile[u + fast_div(u, rt.magic_units) * PADU + OFF * SU];
 }
 
 
@@ -699,7 +711,7 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
         }
         if (seg == 0) return false;
         const int sc = seg + (seg != a.g.nx ? 2 : 0);  // sites per copy
-        lds = static_cast<size_t>(sc) * (units + 1) * 16 +
+        lds = static_cast<size_t>(sc) * (units + row_pad(units, a.nv * sizeof(S) / 4)) * 16 +
               static_cast<size_t>(sc) * 3 * NC * NC * sizeof(typename P::G);
         return lds <= 64 * 1024;
     };
