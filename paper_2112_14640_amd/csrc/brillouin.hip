@@ -351,16 +351,6 @@ __global__ __launch_bounds__(256) void brillouin_kernel(const typename P::G* __r
 // shares it between the d_x = -1 and +1 hops only).  Three waves per SIMD
 // cap the registers at 168 (FP32 and BF16 fit, the segmented forms spill a few values); FP64, whose
 // operands take twice the registers, takes the colour-split form (CS) at three waves per SIMD.
-// Padding (16-byte units) after each site of a row copy in LDS.  The threads of a wave read one element
-// of consecutive RHS at a time, site after site; with the site stride congruent to the span of one site's
-// RHS run (span dwords) modulo the 64 LDS banks, the runs of consecutive sites fall on consecutive banks
-// and a read is free of bank conflicts.  One unit when the span is not a whole number of units.
-__host__ __device__ inline uint32_t row_pad(uint32_t units, uint32_t span) {
-    if (span % 4u != 0) return 1u;
-    const uint32_t p = ((span % 64u) + 64u - (4u * units) % 64u) % 64u / 4u;
-    return p == 0 ? 16u : p;
-}
-
 template <int NC, int RB, bool DAG, class P, int NVC, bool SEG, bool CS = false>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(typename P::R) == 8 && !CS ? 2 : 3))) void brillouin_rows_kernel(const typename P::G* __restrict__ W,
                                                              const typename P::S* __restrict__ in,

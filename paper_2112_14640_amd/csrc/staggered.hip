@@ -128,11 +128,15 @@ __global__ __launch_bounds__(512) void staggered_rows_kernel(const typename P::G
     const int64_t site = rowsite + x;
     const int cy = pos.y, cz = pos.z, ct = pos.t;
     const Unit* src = reinterpret_cast<const Unit*>(in);
+    // sites of the row copy padded to a bank-conflict-free stride
+    const uint32_t PADU = row_pad(rt.units, static_cast<uint32_t>(nv) * static_cast<uint32_t>(sizeof(S)) / 4u,
+                                  static_cast<uint32_t>(sizeof(Unit)) / 4u);
+    const uint32_t SU = rt.units + PADU;  // units per site of the row copy
     uint32_t slot[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const uint32_t u = k * static_cast<uint32_t>(rt.threads) + tt;
-        slot[k] = u + fast_div(u, rt.magic_units);
+        slot[k] = u + fast_div(u, rt.magic_units) * PADU;
     }
     Unit pre[PER];
     const uint32_t row_bytes = static_cast<uint32_t>(rt.row_units * sizeof(Unit));
@@ -148,7 +152,7 @@ __global__ __launch_bounds__(512) void staggered_rows_kernel(const typename P::G
         for (int k = 0; k < PER; ++k) rtile[slot[k]] = pre[k];
     };
     auto at = [&](uint32_t jj) __attribute__((always_inline)) {
-        return reinterpret_cast<const S*>(rtile + jj * (rt.units + 1)) + rg * RB;
+        return reinterpret_cast<const S*>(rtile + jj * SU) + rg * RB;
     };
     auto load_link = [&](cx<R> (&l)[NC][NC], const G* lp, bool adj) __attribute__((always_inline)) {
 #pragma unroll
@@ -167,7 +171,7 @@ __global__ __launch_bounds__(512) void staggered_rows_kernel(const typename P::G
     // row's, used as adjoints), at most LPER complex entries per thread; otherwise every thread
     // loads its own link one direction ahead.
     constexpr int LPER = 2;
-    G* lwin = reinterpret_cast<G*>(sraw + (static_cast<size_t>(rt.S) * (rt.units + 1) * sizeof(Unit) + 15) / 16 * 16);
+    G* lwin = reinterpret_cast<G*>(sraw + (static_cast<size_t>(rt.S) * SU * sizeof(Unit) + 15) / 16 * 16);
     const uint32_t nlink = static_cast<uint32_t>(rt.S) * L;
     G lpre[LPER];
     auto lfetch = [&](int64_t lrow, int mu) __attribute__((always_inline)) {
@@ -294,7 +298,7 @@ __global__ __launch_bounds__(512) void staggered_rows_kernel(const typename P::G
     // streaming stores: the output is not read again by this launch, so its lines should not
     // displace input rows that neighbouring work-groups still read from L2
     for (uint32_t u = tid; u < total; u += blockDim.x)
-        __builtin_nontemporal_store(rtile[u + fast_div(u, rt.magic_units)], dst + u);
+        __builtin_nontemporal_store(rtile[u + fast_div(u, rt.magic_units) * PADU], dst + u);
     if (epi.mode == 1)
         row_epilogue<RB, NC, R, S>(epi, acc, active, 0, nv, rg * RB, j, rt.S, tix, reinterpret_cast<double*>(sraw));
 }
@@ -314,7 +318,8 @@ bool launch_rows(const StencilArgs& a, int nv, typename P::R diag, hipStream_t s
         const int nrg = nv / RB;
         const int64_t rows = a.g.vol / a.g.nx;
         const int64_t threads = static_cast<int64_t>(a.g.nx) * nrg;
-        const size_t lds = static_cast<size_t>(a.g.nx) * (units + 1) * ub;
+        const uint32_t pad = row_pad(units, static_cast<uint32_t>(nv * sizeof(S) / 4), static_cast<uint32_t>(ub / 4));
+        const size_t lds = static_cast<size_t>(a.g.nx) * (units + pad) * ub;
         if (threads < 64 || threads > 512 || lds > 64 * 1024) return false;
         RowTile rt{};
         rt.R = 1;

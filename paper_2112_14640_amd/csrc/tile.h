@@ -94,7 +94,16 @@ struct RowUnits {
 };
 
 // Bytes of LDS for one staged row tile (site stride padded by one 16-byte unit).
-inline size_t row_tile_lds(int S, int units) { return static_cast<size_t>(S) * (units + 1) * 16; }
+// Padding (in row units of udw dwords) after each site of a row copy in LDS.  The threads of a wave
+// read one element of consecutive RHS at a time, site after site; with the site stride congruent, modulo
+// the 64 LDS banks, to the span (dwords) of one site's RHS run, the runs of consecutive sites fall on
+// consecutive banks and a read is free of bank conflicts.  One unit when the span is not a whole number
+// of units or already covers the 64 banks (a wider pad measured slower there).
+__host__ __device__ inline uint32_t row_pad(uint32_t units, uint32_t span, uint32_t udw = 4) {
+    if (span % udw != 0 || span > 64u) return 1u;
+    return ((span % 64u) + 64u - (udw * units) % 64u) % 64u / udw;
+}
+inline size_t row_tile_lds(int S, int units, uint32_t pad) { return static_cast<size_t>(S) * (units + pad) * 16; }
 
 // Row processed by tile number T (after the XCD remap) in the order of RowTile.  The divisors
 // are uniform over the work-group; the magic multiplies keep them on the scalar unit.
@@ -174,9 +183,9 @@ constexpr size_t kRowLdsCap = 96 * 1024;
 
 // Row tiles are used (variant 4) when one row of every RHS fits: 64..512 threads and at
 // most kRowLdsCap bytes of LDS (and what the device allows).  Returns the rows per tile (1) or 0.
-inline int choose_tile_rows(int, int64_t rows, int nx, int units, int nrg) {
+inline int choose_tile_rows(int, int64_t rows, int nx, int units, int nrg, uint32_t pad) {
     const int64_t threads = static_cast<int64_t>(nx) * nrg;
-    const size_t lds = row_tile_lds(nx, units);
+    const size_t lds = row_tile_lds(nx, units, pad);
     if (rows >= 1 && threads >= 64 && threads <= 512 && lds <= kRowLdsCap && lds <= max_lds_per_block()) return 1;
     return 0;
 }

@@ -305,12 +305,15 @@ __global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* _
     const u32x4* src = reinterpret_cast<const u32x4*>(in);
     if constexpr (NVC > 0) nv = NVC;
 
-    // unit k of this thread: k * threads + tt of the row copy; its padded LDS slot
+    // unit k of this thread: k * threads + tt of the row copy; its padded LDS slot (sites padded to a
+    // bank-conflict-free stride)
+    const uint32_t PADU = row_pad(rt.units, static_cast<uint32_t>(nv) * static_cast<uint32_t>(sizeof(S)) / 4u);
+    const uint32_t SU = rt.units + PADU;  // units per site of the row copy
     uint32_t slot[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const uint32_t u = k * static_cast<uint32_t>(rt.threads) + tt;
-        slot[k] = u + fast_div(u, rt.magic_units);
+        slot[k] = u + fast_div(u, rt.magic_units) * PADU;
     }
     u32x4 pre[PER];
     const uint32_t row_bytes = static_cast<uint32_t>(rt.row_units) * 16u;
@@ -325,7 +328,7 @@ __global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* _
         for (int k = 0; k < PER; ++k) rtile[slot[k]] = pre[k];
     };
     auto at = [&](uint32_t jj) __attribute__((always_inline)) {
-        return reinterpret_cast<const S*>(rtile + jj * (rt.units + 1)) + rg * RB;
+        return reinterpret_cast<const S*>(rtile + jj * SU) + rg * RB;
     };
 
     // LL: the links of the direction being consumed are staged in LDS after the row tile, one
@@ -335,7 +338,7 @@ __global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* _
     using G = typename P::G;
     constexpr int NRG = NVC > 0 ? NVC / RB : 1;
     constexpr int LPER = LL ? (L + NRG - 1) / NRG : 1;
-    G* lwin = reinterpret_cast<G*>(rtile + rt.S * (rt.units + 1));
+    G* lwin = reinterpret_cast<G*>(rtile + rt.S * SU);
     const uint32_t nlink = static_cast<uint32_t>(rt.S) * L;
     G lpre[LPER];
     auto lfetch = [&](int64_t lrow, int mu) __attribute__((always_inline)) {
@@ -467,7 +470,7 @@ __global__ __launch_bounds__(512) void wilson_rows_kernel(const typename P::G* _
     // streaming stores: the output is not read again by this launch, so its lines should not
     // displace input rows that neighbouring work-groups still read from L2
     for (uint32_t u = tid; u < total; u += blockDim.x)
-        __builtin_nontemporal_store(rtile[u + fast_div(u, rt.magic_units)], dst + u);
+        __builtin_nontemporal_store(rtile[u + fast_div(u, rt.magic_units) * PADU], dst + u);
     if (epi.mode == 1)
         row_epilogue<RB, NC * 4, R, S>(epi, flat, active, 0, nv, rg * RB, j, rt.S, tix,
                                        reinterpret_cast<double*>(rtile));
@@ -481,7 +484,8 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
     const int units = static_cast<int>(block_bytes / 16);
     const int nrg = a.nv / RB;
     const int64_t rows = a.g.vol / a.g.nx;
-    const int Rr = choose_tile_rows(a.variant, rows, a.g.nx, units, nrg);
+    const uint32_t pad = row_pad(units, static_cast<uint32_t>(a.nv * sizeof(S) / 4));
+    const int Rr = choose_tile_rows(a.variant, rows, a.g.nx, units, nrg, pad);
     if (Rr == 0) return false;
     RowTile rt;
     rt.R = Rr;
@@ -498,7 +502,7 @@ bool launch_rows(const StencilArgs& a, hipStream_t st) {
     rt.magic_row_units = div_magic(rt.row_units);
     if (!row_order(4, a.g, rt)) return false;
     const int block = (rt.threads + 63) / 64 * 64;
-    size_t lds = row_tile_lds(rt.S, units);
+    size_t lds = row_tile_lds(rt.S, units, pad);
     // with N_v = 12 and one RHS per thread each direction's links are staged in LDS too: N_c^2
     // entries per site after the row tile
     const size_t lds_ll = lds + (static_cast<size_t>(rt.S) * NC * NC * sizeof(typename P::G) + 15) / 16 * 16;
